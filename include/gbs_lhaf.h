@@ -1,0 +1,147 @@
+/*
+ * gbs_lhaf.h -- C ABI of the MI355X (gfx950) loop-hafnian library.
+ *
+ * The library evaluates the loop hafnian of a complex symmetric matrix by the
+ * power-trace subset sum that Quesada et al., "Quadratic speedup for simulating
+ * Gaussian boson sampling" (arXiv:2010.15595, "the paper") benchmark in Sec. IV,
+ * and the pure-state photon-number probability of Sec. II, Eq. (12), built on
+ * it.  All arithmetic runs in HIP kernels on the GPU; the host code only
+ * validates, expands photon patterns, factorises the 2M x 2M matrix Q and
+ * assembles the final probability.
+ *
+ * Conventions
+ *   - Complex numbers are gbs_z {re, im}: the layout of C99 double _Complex,
+ *     std::complex<double> and torch.complex128.
+ *   - Matrices are row-major with an explicit leading dimension (in elements).
+ *   - Host-pointer entry points are synchronous.  Device-pointer entry points
+ *     are ordered on the HIP stream passed in (NULL = the null stream) and
+ *     return before the GPU work finishes.
+ *   - The return code is the only error channel.  On error, outputs are left
+ *     untouched and gbs_last_error() returns a thread-local description.
+ *   - The caller owns every buffer it passes.  The library owns per-device
+ *     workspace, created by gbs_init() and released by gbs_finalize().
+ *   - lhaf(0 x 0) = 1.  An odd dimension is padded with one vertex that has
+ *     loop weight 1 and no edges (the value is unchanged).  Pairs of the
+ *     subset sum are (i, i + n), n = ceil(N / 2).
+ *   - Largest supported dimension after expansion: GBS_MAX_DIM.
+ */
+#ifndef GBS_LHAF_H
+#define GBS_LHAF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GBS_MAX_DIM 64
+
+typedef struct { double re, im; } gbs_z;
+
+typedef enum {
+    GBS_OK = 0,
+    GBS_E_ARG = -1,           /* null pointer, negative size, bad enum, bad leading dimension */
+    GBS_E_NOT_SYMMETRIC = -2, /* |A_ij - A_ji| > 1e-12 * max|A| */
+    GBS_E_NONFINITE = -3,     /* NaN or Inf in an input */
+    GBS_E_TOO_LARGE = -4,     /* expanded dimension > GBS_MAX_DIM, or batch too large */
+    GBS_E_NOT_PURE = -5,      /* Q does not describe a pure state (probability only) */
+    GBS_E_NOT_PD = -6,        /* Q singular or not Hermitian positive definite */
+    GBS_E_DEVICE = -7,        /* no usable GPU, or a HIP call failed */
+    GBS_E_NOMEM = -8,         /* device or host allocation failed */
+    GBS_E_UNSUPPORTED = -9    /* valid request the library does not implement */
+} gbs_status;
+
+typedef enum {
+    GBS_FP64 = 0,      /* all steps in IEEE binary64 */
+    GBS_FP32_COMP = 1  /* reserved: complex FP32 subset terms, FP64 reduction */
+} gbs_precision;
+
+/* Optional diagnostics of one loop-hafnian evaluation. */
+typedef struct {
+    double abs_sum;        /* sum over subsets of |t_S|                         */
+    double kappa;          /* abs_sum / |lhaf| (cancellation ratio; inf if 0)   */
+    uint64_t subset_terms; /* 2^n                                               */
+    double kernel_ms;      /* GPU time of the subset sum (HIP events)           */
+    int32_t n_pairs;       /* n                                                 */
+    int32_t launches;      /* kernel launches issued                            */
+} gbs_diag;
+
+/* ---- library lifetime ---------------------------------------------------- */
+
+/* Select `device` (HIP ordinal) and create its workspace.  Idempotent per
+ * device.  Returns GBS_E_DEVICE when no GPU is visible. */
+gbs_status gbs_init(int device);
+/* Release all device workspace created by gbs_init.  Safe to call twice. */
+void gbs_finalize(void);
+const char *gbs_status_string(gbs_status status);
+/* Thread-local detail for the last failing call on this thread ("" if none). */
+const char *gbs_last_error(void);
+int32_t gbs_max_dim(void);
+
+/* ---- host helpers (no GPU needed) ---------------------------------------- */
+
+/* Pattern expansion, Sec. II (text after Eqs. (7) and (11)): row/column i of B
+ * (M x M, leading dim ldb) repeated mult[i] times, dropped when mult[i] = 0,
+ * then the main diagonal replaced by gamma repeated the same way (filldiag).
+ * gamma NULL keeps B's diagonal; mult NULL means all ones.  Writes the
+ * N x N result (N = sum mult) row-major into out (capacity out_cap elements)
+ * and N into *N_out.  B must be symmetric. */
+gbs_status gbs_expand(const gbs_z *B, int32_t M, int64_t ldb, const gbs_z *gamma,
+                      const int32_t *mult, gbs_z *out, int64_t out_cap, int32_t *N_out);
+
+/* Pure-state parameters from Q = Sigma + I/2 (2M x 2M, Eq. (3)) and the mean
+ * vector alpha = [a; conj(a)] (2M, Eq. (8)):
+ *   B      = (X (I - Q^-1))[:M, :M]                 (Eq. (4); A = B (+) conj(B))
+ *   gamma  = (Q^-1 alpha)[M:] = conj(a) - B a       (Eq. (9), see note)
+ *   p_vac  = exp(-alpha^H Q^-1 alpha / 2) / sqrt(det Q)   (Eq. (10))
+ * Note: Eq. (9) printed with this block order pairs the loop weights with
+ * conj(B); the half used here is the one that pairs with B, which is what a
+ * Fock-space computation of the same state confirms.  Any of B_out, gamma_out,
+ * p_vac_out may be NULL.  Errors: GBS_E_NOT_PD for singular / non-positive Q,
+ * GBS_E_NOT_PURE when A is not of the form B (+) conj(B) to 1e-10. */
+gbs_status gbs_pure_state(const gbs_z *Q, const gbs_z *alpha, int32_t M, gbs_z *B_out,
+                          gbs_z *gamma_out, double *p_vac_out);
+
+/* ---- single evaluations, host pointers, synchronous ---------------------- */
+
+/* lhaf(filldiag(A_S, gamma_S)) for the expansion described at gbs_expand.
+ * A: M x M symmetric, leading dim lda.  *out receives the loop hafnian.
+ * diag may be NULL. */
+gbs_status gbs_lhaf(const gbs_z *A, int32_t M, int64_t lda, const gbs_z *gamma,
+                    const int32_t *mult, gbs_precision prec, gbs_z *out, gbs_diag *diag);
+
+/* haf(A) (Eq. (6)) of an N x N symmetric matrix: the loop hafnian of A with a
+ * zero diagonal.  Odd N gives 0. */
+gbs_status gbs_haf(const gbs_z *A, int32_t N, int64_t lda, gbs_precision prec, gbs_z *out,
+                   gbs_diag *diag);
+
+/* Pure-state photon-number probability, Eq. (12):
+ *   p(S) = p(vac) |lhaf(filldiag(B_S, gamma_S))|^2 / prod_i s_i!
+ * Q: 2M x 2M (row-major, dense), alpha: 2M, pattern: M photon counts >= 0.
+ * lhaf_out and diag may be NULL. */
+gbs_status gbs_probability(const gbs_z *Q, const gbs_z *alpha, const int32_t *pattern,
+                           int32_t M, gbs_precision prec, double *p_out, gbs_z *lhaf_out,
+                           gbs_diag *diag);
+
+/* Signed subset terms t_S of the power-trace sum for an explicit list of pair
+ * subsets (bit i of masks[j] set = pair (i, i+n) kept).  A: N x N, its diagonal
+ * holds the loop weights.  terms_out[j] receives t_S; sum over all 2^n masks
+ * gives lhaf(A).  Host pointers, synchronous.  Diagnostic / parity use. */
+gbs_status gbs_lhaf_terms(const gbs_z *A, int32_t N, int64_t lda, const uint64_t *masks,
+                          int64_t count, gbs_precision prec, gbs_z *terms_out);
+
+/* ---- device-resident evaluation, stream-ordered -------------------------- */
+
+/* lhaf of the N x N row-major matrix A_dev (device memory, diagonal = loop
+ * weights, leading dim N).  Writes the result to out_dev[0] and, when
+ * abs_sum_dev is non-NULL, sum_S |t_S| to abs_sum_dev[0] (device memory).
+ * Symmetry is not checked here (the caller owns the device data).  Ordered on
+ * `stream` (a hipStream_t, NULL = null stream); asynchronous. */
+gbs_status gbs_lhaf_device(const gbs_z *A_dev, int32_t N, gbs_precision prec, gbs_z *out_dev,
+                           double *abs_sum_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBS_LHAF_H */
