@@ -140,6 +140,37 @@ gbs_status gbs_lhaf_terms(const gbs_z *A, int32_t N, int64_t lda, const uint64_t
 gbs_status gbs_lhaf_device(const gbs_z *A_dev, int32_t N, gbs_precision prec, gbs_z *out_dev,
                            double *abs_sum_dev, void *stream);
 
+/* ---- diagnostics --------------------------------------------------------- */
+
+/* Per-kernel timing of the subset-sum kernels, measured with HIP events
+ * recorded on the launch stream around every launch while enabled. */
+typedef struct {
+    double charpoly_ms;        /* summed durations of the per-subset kernels (Hessenberg + La Budde) */
+    double series_ms;          /* summed durations of the per-subset series kernels                 */
+    double reduce_ms;          /* summed durations of the final reductions                          */
+    int64_t charpoly_launches;
+    int64_t series_launches;
+    int64_t reduce_launches;
+    double charpoly_flops;     /* algorithmic flops of the profiled subsets (see gbs_yardstick_flops) */
+    double subset_terms;       /* subsets processed by the profiled launches                        */
+} gbs_profile;
+
+/* on = 1 clears the counters and starts recording; on = 0 stops recording. */
+gbs_status gbs_profile_enable(int on);
+/* Waits for the recorded events, writes the totals since the last enable or
+ * read into *out and clears them. */
+gbs_status gbs_profile_read(gbs_profile *out);
+/* Algorithmic real-flop count of the subset sum of an N x N loop hafnian:
+ * sum over subset sizes s of C(n, s) [(40/3) m^3 + (4/3) m^3 + 8 min(n-1, m-1) m^2],
+ * m = 2s -- Householder Hessenberg reduction, characteristic polynomial and the
+ * loop-term mat-vecs of the power-trace method, one complex FMA = 8 flops. */
+double gbs_yardstick_flops(int32_t N);
+
+/* Runs the device self-check of the wavefront cross-lane sums, broadcasts and
+ * lane shifts the kernels rely on, against host arithmetic.  *failures
+ * receives the number of mismatching lanes (0 = pass). */
+gbs_status gbs_selftest(int32_t *failures);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,9 +51,11 @@ def _lib():
             getattr(lib, f"oracle_lhaf_dp_{sfx}").argtypes = [dp, ctypes.c_int, rp]
             getattr(lib, f"oracle_lhaf_pt_{sfx}").argtypes = [dp, ctypes.c_int, ctypes.c_int, rp, rp]
             getattr(lib, f"oracle_term_{sfx}").argtypes = [dp, ctypes.c_int, ctypes.c_ulonglong, rp]
+            getattr(lib, f"oracle_terms_{sfx}").argtypes = [dp, ctypes.c_int, ctypes.POINTER(ctypes.c_ulonglong),
+                                                            ctypes.c_longlong, ctypes.c_int, rp]
             getattr(lib, f"oracle_charpoly_{sfx}").argtypes = [dp, ctypes.c_int, rp]
             getattr(lib, f"oracle_power_traces_{sfx}").argtypes = [dp, ctypes.c_int, ctypes.c_int, rp]
-            for name in ("lhaf_dp", "lhaf_pt", "term", "charpoly", "power_traces"):
+            for name in ("lhaf_dp", "lhaf_pt", "term", "terms", "charpoly", "power_traces"):
                 getattr(lib, f"oracle_{name}_{sfx}").restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
         _LIB = lib
@@ -121,6 +123,19 @@ def term(A, mask, prec="ld"):
     out, op = _out(2, prec)
     _check(getattr(_lib(), f"oracle_term_{sfx}")(ap, N, ctypes.c_ulonglong(int(mask)), op), "term")
     return complex(float(out[0]), float(out[1]))
+
+
+def terms(A, masks, prec="ld", nthreads=0):
+    """Signed subset terms for an array of masks (threads over the list)."""
+    A, ap = _as_input(A)
+    N = A.shape[0]
+    sfx = _prec(prec)[0]
+    mk = np.ascontiguousarray(masks, dtype=np.uint64)
+    out, op = _out(2 * mk.shape[0], prec)
+    _check(getattr(_lib(), f"oracle_terms_{sfx}")(ap, N, mk.ctypes.data_as(ctypes.POINTER(ctypes.c_ulonglong)),
+                                                  mk.shape[0], int(nthreads), op), "terms")
+    o = out.astype(np.float64)
+    return o[0::2] + 1j * o[1::2]
 
 
 def charpoly(M, prec="ld"):

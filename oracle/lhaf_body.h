@@ -291,6 +291,43 @@ int SFX(oracle_term)(const double *A, int N, unsigned long long mask, REAL *out)
     return 0;
 }
 
+/* Signed terms for a list of subset masks (each computed exactly as in
+ * oracle_term), spread over threads; out receives 2 * count reals. */
+int SFX(oracle_terms)(const double *A, int N, const unsigned long long *masks, long long count, int nthreads,
+                      REAL *out)
+{
+    if (N < 1 || N > ORACLE_PT_MAX_N || !A || !out || count < 0 || (count > 0 && !masks)) return -1;
+    int Np;
+    CPLX *Ap = SFX(padded)(A, N, &Np);
+    if (!Ap) return -2;
+    int n = Np / 2;
+    for (long long j = 0; j < count; ++j)
+        if (n < 64 && (masks[j] >> n) != 0) { free(Ap); return -1; }
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        SFX(ws_t) ws;
+        int bad = SFX(ws_alloc)(&ws, Np);
+        if (bad) {
+#pragma omp atomic write
+            err = bad;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (long long j = 0; j < count; ++j) {
+            if (bad) continue;
+            CPLX t = SFX(subset_term)(Ap, Np, masks[j], &ws);
+            out[2 * j] = ZRE(t);
+            out[2 * j + 1] = ZIM(t);
+        }
+        SFX(ws_free)(&ws);
+    }
+    free(Ap);
+    return err;
+}
+
 /* Whole loop hafnian by the subset sum.  Subsets are visited in mask order in
  * fixed chunks of ORACLE_CHUNK masks; each chunk is summed in order with
  * Neumaier compensation and the chunk results are combined in chunk order, so

@@ -1,0 +1,27 @@
+"""MI355X (gfx950) loop-hafnian library for Gaussian boson sampling.
+
+The loop hafnian of a complex symmetric matrix by the power-trace subset sum
+(Quesada et al., arXiv:2010.15595, Sec. IV) and the pure-state photon-number
+probability of Sec. II, Eq. (12), computed by hand-written HIP kernels behind
+the C ABI of include/gbs_lhaf.h.  This package is the thin Python binding.
+"""
+from ._lib import (  # noqa: F401
+    GBS_FP32_COMP,
+    GBS_FP64,
+    GbsError,
+    expand,
+    finalize,
+    haf,
+    init,
+    lhaf,
+    lhaf_device,
+    lhaf_terms,
+    lib,
+    max_dim,
+    probability,
+    profile_enable,
+    profile_read,
+    pure_state,
+    selftest,
+    yardstick_flops,
+)

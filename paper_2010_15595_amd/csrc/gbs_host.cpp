@@ -1,0 +1,706 @@
+// Host side of the gbs_lhaf C ABI: argument validation, photon-pattern
+// expansion, the pure-state parameters of Q (Cholesky factorisation on the
+// host, O(M^3) for M <= a few hundred), device workspace and the launch
+// schedule of the subset-sum kernels.  Every step of the subset sum itself runs
+// in the HIP kernels of lhaf_kernels.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gbs_lhaf.h"
+#include "lhaf_kernels.h"
+
+using cplx = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gbs_status fail(gbs_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(call)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(e_ == hipErrorOutOfMemory ? GBS_E_NOMEM : GBS_E_DEVICE, "%s: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                       \
+    } while (0)
+
+constexpr uint64_t kChunk = 1ull << 18;  // subsets per phase-1 launch
+constexpr int kPerThread = 8;            // subsets per lane in phase 2
+
+uint64_t binom_host(int a, int b) {
+    if (b < 0 || b > a) return 0;
+    uint64_t r = 1;
+    for (int i = 1; i <= b; ++i) r = r * (uint64_t)(a - b + i) / (uint64_t)i;
+    return r;
+}
+
+// Per-device workspace.  All library calls take g_mutex, so one context is
+// used by one call at a time; `done` orders reuse across caller streams.
+struct DevCtx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr, t0 = nullptr, t1 = nullptr;
+    uint64_t* binom = nullptr;
+    double2* A0 = nullptr;      // 64 x 64
+    double2* dvec = nullptr;    // 64
+    double2* Ain = nullptr;     // host-call staging, 64 x 64
+    double2* res = nullptr;     // [0] lhaf, [1] (abs_sum, -)
+    double2* E = nullptr;
+    size_t E_cap = 0;           // double2 elements
+    double* partials = nullptr;
+    size_t partials_cap = 0;    // partial records
+    uint64_t* masks = nullptr;
+    double2* terms = nullptr;
+    size_t masks_cap = 0;
+};
+
+std::mutex g_mutex;
+std::map<int, DevCtx*> g_ctx;
+
+// Optional per-launch timing (gbs_profile_enable / gbs_profile_read).
+enum ProfKind { kProfCharpoly = 0, kProfSeries = 1, kProfReduce = 2 };
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double flops, subsets;
+};
+bool g_prof = false;
+std::vector<ProfRec> g_prof_recs;
+
+double subset_flops(int n, int s) {
+    const double m = 2.0 * s;
+    return (40.0 / 3.0) * m * m * m + (4.0 / 3.0) * m * m * m + 8.0 * std::min(n - 1.0, m - 1.0) * m * m;
+}
+
+// Records an event pair around `launch` when profiling is on.
+template <class F>
+hipError_t timed_launch(int kind, double flops, double subsets, hipStream_t st, F&& launch) {
+    if (!g_prof) return launch();
+    ProfRec r{kind, nullptr, nullptr, flops, subsets};
+    hipError_t e = hipEventCreate(&r.a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&r.b);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(r.a, st);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(r.b, st);
+    g_prof_recs.push_back(r);
+    return e;
+}
+
+gbs_status ensure_buffer(void** p, size_t* cap, size_t need, size_t elem) {
+    if (*cap >= need) return GBS_OK;
+    if (*p) hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    hipError_t e = hipMalloc(p, need * elem);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(GBS_E_NOMEM, "hipMalloc(%zu bytes) failed: %s", need * elem, hipGetErrorString(e));
+    }
+    *cap = need;
+    return GBS_OK;
+}
+
+gbs_status ctx_create(int device, DevCtx** out) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(GBS_E_DEVICE, "no HIP device available");
+    if (device < 0 || device >= count) return fail(GBS_E_DEVICE, "device %d out of range (%d devices)", device, count);
+    HIP_TRY(hipSetDevice(device));
+    DevCtx* c = new DevCtx();
+    c->device = device;
+    HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
+    HIP_TRY(hipEventCreate(&c->t0));
+    HIP_TRY(hipEventCreate(&c->t1));
+    std::vector<uint64_t> tab(gbs::kBinomStride * gbs::kBinomStride, 0);
+    for (int a = 0; a < gbs::kBinomStride; ++a)
+        for (int b = 0; b < gbs::kBinomStride; ++b) tab[a * gbs::kBinomStride + b] = binom_host(a, b);
+    HIP_TRY(hipMalloc((void**)&c->binom, tab.size() * sizeof(uint64_t)));
+    HIP_TRY(hipMemcpy(c->binom, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc((void**)&c->A0, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
+    HIP_TRY(hipMalloc((void**)&c->dvec, sizeof(double2) * GBS_MAX_DIM));
+    HIP_TRY(hipMalloc((void**)&c->Ain, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
+    HIP_TRY(hipMalloc((void**)&c->res, sizeof(double2) * 2));
+    HIP_TRY(hipEventRecord(c->done, c->stream));
+    *out = c;
+    return GBS_OK;
+}
+
+void ctx_destroy(DevCtx* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    hipFree(c->binom);
+    hipFree(c->A0);
+    hipFree(c->dvec);
+    hipFree(c->Ain);
+    hipFree(c->res);
+    hipFree(c->E);
+    hipFree(c->partials);
+    hipFree(c->masks);
+    hipFree(c->terms);
+    if (c->done) hipEventDestroy(c->done);
+    if (c->t0) hipEventDestroy(c->t0);
+    if (c->t1) hipEventDestroy(c->t1);
+    if (c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+// Context of the current HIP device, created on first use.
+gbs_status current_ctx(DevCtx** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(GBS_E_DEVICE, "hipGetDevice failed");
+    auto it = g_ctx.find(dev);
+    if (it != g_ctx.end()) {
+        *out = it->second;
+        return GBS_OK;
+    }
+    DevCtx* c = nullptr;
+    gbs_status st = ctx_create(dev, &c);
+    if (st != GBS_OK) return st;
+    g_ctx[dev] = c;
+    *out = c;
+    return GBS_OK;
+}
+
+bool finite_z(const gbs_z& z) { return std::isfinite(z.re) && std::isfinite(z.im); }
+
+gbs_status check_matrix(const gbs_z* A, int32_t N, int64_t lda, const char* what, bool need_sym) {
+    if (N < 0) return fail(GBS_E_ARG, "%s: negative dimension %d", what, N);
+    if (N == 0) return GBS_OK;
+    if (!A) return fail(GBS_E_ARG, "%s: null pointer", what);
+    if (lda < N) return fail(GBS_E_ARG, "%s: leading dimension %lld < %d", what, (long long)lda, N);
+    double amax = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            const gbs_z& z = A[(int64_t)i * lda + j];
+            if (!finite_z(z)) return fail(GBS_E_NONFINITE, "%s: non-finite entry at (%d, %d)", what, i, j);
+            amax = std::max(amax, std::hypot(z.re, z.im));
+        }
+    if (need_sym) {
+        const double tol = 1e-12 * amax;
+        for (int i = 0; i < N; ++i)
+            for (int j = i + 1; j < N; ++j) {
+                const gbs_z& a = A[(int64_t)i * lda + j];
+                const gbs_z& b = A[(int64_t)j * lda + i];
+                if (std::hypot(a.re - b.re, a.im - b.im) > tol)
+                    return fail(GBS_E_NOT_SYMMETRIC, "%s: entries (%d, %d) and (%d, %d) differ", what, i, j, j, i);
+            }
+    }
+    return GBS_OK;
+}
+
+gbs_status expand_impl(const gbs_z* B, int32_t M, int64_t ldb, const gbs_z* gamma, const int32_t* mult,
+                       std::vector<gbs_z>& out, int32_t* N_out) {
+    if (M < 0) return fail(GBS_E_ARG, "negative M");
+    if (M > 0 && !B) return fail(GBS_E_ARG, "null matrix");
+    if (M > 0 && ldb < M) return fail(GBS_E_ARG, "leading dimension %lld < M = %d", (long long)ldb, M);
+    gbs_status st = check_matrix(B, M, ldb, "A", true);
+    if (st != GBS_OK) return st;
+    int64_t N = 0;
+    for (int i = 0; i < M; ++i) {
+        const int s = mult ? mult[i] : 1;
+        if (s < 0) return fail(GBS_E_ARG, "negative multiplicity %d at mode %d", s, i);
+        N += s;
+        if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "expanded dimension exceeds %d", GBS_MAX_DIM);
+    }
+    if (gamma)
+        for (int i = 0; i < M; ++i)
+            if ((mult ? mult[i] : 1) > 0 && !finite_z(gamma[i]))
+                return fail(GBS_E_NONFINITE, "non-finite loop weight at mode %d", i);
+    std::vector<int> idx;
+    idx.reserve(N);
+    for (int i = 0; i < M; ++i)
+        for (int r = 0; r < (mult ? mult[i] : 1); ++r) idx.push_back(i);
+    out.assign((size_t)N * N, gbs_z{0.0, 0.0});
+    for (int64_t a = 0; a < N; ++a)
+        for (int64_t b = 0; b < N; ++b) out[a * N + b] = B[(int64_t)idx[a] * ldb + idx[b]];
+    if (gamma)
+        for (int64_t a = 0; a < N; ++a) out[a * N + a] = gamma[idx[a]];
+    *N_out = (int32_t)N;
+    return GBS_OK;
+}
+
+// Subset-sum schedule on prepared workspace (ctx->A0, ctx->dvec).
+gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* abs_dev, int* launches) {
+    const int n = Np / 2;
+    int nl = 0;
+    if (n == 0) {
+        HIP_TRY(gbs::launch_scalar_set(out_dev, make_double2(1.0, 0.0), abs_dev, 1.0, st));
+        if (launches) *launches = 1;
+        return GBS_OK;
+    }
+    const int D = n + 1;
+    uint64_t max_len = 0, total_blocks = 0;
+    const uint64_t per_block = 64ull * kPerThread;
+    for (int s = 1; s <= n; ++s) {
+        const uint64_t cnt = binom_host(n, s);
+        for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
+            const uint64_t len = std::min(kChunk, cnt - st0);
+            max_len = std::max(max_len, len);
+            total_blocks += (len + per_block - 1) / per_block;
+        }
+    }
+    gbs_status s1 = ensure_buffer((void**)&c->E, &c->E_cap, (size_t)max_len * 2 * (D + 1), sizeof(double2));
+    if (s1 != GBS_OK) return s1;
+    s1 = ensure_buffer((void**)&c->partials, &c->partials_cap, (size_t)total_blocks * 5, sizeof(double));
+    if (s1 != GBS_OK) return s1;
+    uint64_t poff = 0;
+    for (int s = 1; s <= n; ++s) {
+        const uint64_t cnt = binom_host(n, s);
+        const double sign = ((n - s) & 1) ? -1.0 : 1.0;
+        for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
+            const uint64_t len = std::min(kChunk, cnt - st0);
+            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, c->E};
+            HIP_TRY(timed_launch(kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
+                                 [&] { return gbs::launch_charpoly(p1, st); }));
+            gbs::LaunchPhase2 p2{c->E, len, D, sign, kPerThread, c->partials + 5 * poff, nullptr};
+            HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, st, [&] { return gbs::launch_series(n, p2, st); }));
+            poff += (len + per_block - 1) / per_block;
+            nl += 2;
+        }
+    }
+    HIP_TRY(timed_launch(kProfReduce, 0.0, 0.0, st, [&] {
+        return gbs::launch_final_reduce(c->partials, (int64_t)poff, out_dev, abs_dev, st);
+    }));
+    if (launches) *launches = nl + 1;
+    return GBS_OK;
+}
+
+// Full evaluation of an expanded host matrix (N x N, diagonal = loop weights).
+gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* diag) {
+    DevCtx* c = nullptr;
+    gbs_status st = current_ctx(&c);
+    if (st != GBS_OK) return st;
+    const int Np = N + (N & 1);
+    HIP_TRY(hipStreamWaitEvent(c->stream, c->done, 0));
+    if (N > 0) HIP_TRY(hipMemcpyAsync(c->Ain, A, sizeof(gbs_z) * (size_t)N * N, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipEventRecord(c->t0, c->stream));
+    if (Np > 0) HIP_TRY(gbs::launch_prep(c->Ain, N, N, Np, c->A0, c->dvec, c->stream));
+    int launches = 0;
+    st = run_sum(c, Np, c->stream, c->res, reinterpret_cast<double*>(c->res + 1), &launches);
+    if (st != GBS_OK) return st;
+    HIP_TRY(hipEventRecord(c->t1, c->stream));
+    double2 h[2];
+    HIP_TRY(hipMemcpyAsync(h, c->res, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipEventRecord(c->done, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    out->re = h[0].x;
+    out->im = h[0].y;
+    if (diag) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, c->t0, c->t1);
+        const double mag = std::hypot(h[0].x, h[0].y);
+        diag->abs_sum = h[1].x;
+        diag->kappa = mag > 0 ? h[1].x / mag : INFINITY;
+        diag->subset_terms = (Np / 2) >= 64 ? 0 : (1ull << (Np / 2));
+        diag->kernel_ms = ms;
+        diag->n_pairs = Np / 2;
+        diag->launches = launches;
+    }
+    return GBS_OK;
+}
+
+// Cholesky factorisation Q = L L^H of a Hermitian matrix (row-major, n x n).
+bool cholesky(std::vector<cplx>& L, int n) {
+    for (int j = 0; j < n; ++j) {
+        double d = L[j * n + j].real();
+        for (int k = 0; k < j; ++k) d -= std::norm(L[j * n + k]);
+        if (!(d > 0.0)) return false;
+        const double ljj = std::sqrt(d);
+        L[j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            cplx s = L[i * n + j];
+            for (int k = 0; k < j; ++k) s -= L[i * n + k] * std::conj(L[j * n + k]);
+            L[i * n + j] = s / ljj;
+        }
+        for (int k = j + 1; k < n; ++k) L[j * n + k] = 0.0;
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+gbs_status gbs_init(int device) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (g_ctx.count(device)) {
+        hipSetDevice(device);
+        return GBS_OK;
+    }
+    DevCtx* c = nullptr;
+    gbs_status st = ctx_create(device, &c);
+    if (st != GBS_OK) return st;
+    g_ctx[device] = c;
+    return GBS_OK;
+}
+
+void gbs_finalize(void) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    for (auto& kv : g_ctx) ctx_destroy(kv.second);
+    g_ctx.clear();
+}
+
+const char* gbs_status_string(gbs_status s) {
+    switch (s) {
+        case GBS_OK: return "ok";
+        case GBS_E_ARG: return "invalid argument";
+        case GBS_E_NOT_SYMMETRIC: return "matrix not symmetric";
+        case GBS_E_NONFINITE: return "non-finite input";
+        case GBS_E_TOO_LARGE: return "problem too large";
+        case GBS_E_NOT_PURE: return "state is not pure";
+        case GBS_E_NOT_PD: return "Q is not Hermitian positive definite";
+        case GBS_E_DEVICE: return "GPU device error";
+        case GBS_E_NOMEM: return "out of memory";
+        case GBS_E_UNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+const char* gbs_last_error(void) { return g_last_error.c_str(); }
+
+int32_t gbs_max_dim(void) { return GBS_MAX_DIM; }
+
+gbs_status gbs_expand(const gbs_z* B, int32_t M, int64_t ldb, const gbs_z* gamma, const int32_t* mult, gbs_z* out,
+                      int64_t out_cap, int32_t* N_out) {
+    if (!N_out) return fail(GBS_E_ARG, "null N_out");
+    std::vector<gbs_z> tmp;
+    int32_t N = 0;
+    gbs_status st = expand_impl(B, M, ldb, gamma, mult, tmp, &N);
+    if (st != GBS_OK) return st;
+    if ((int64_t)N * N > out_cap || (N > 0 && !out))
+        return fail(GBS_E_ARG, "output capacity %lld < %d", (long long)out_cap, N * N);
+    if (N > 0) std::memcpy(out, tmp.data(), sizeof(gbs_z) * tmp.size());
+    *N_out = N;
+    return GBS_OK;
+}
+
+gbs_status gbs_pure_state(const gbs_z* Q, const gbs_z* alpha, int32_t M, gbs_z* B_out, gbs_z* gamma_out,
+                          double* p_vac_out) {
+    if (M < 0) return fail(GBS_E_ARG, "negative M");
+    if (M > 0 && (!Q || !alpha)) return fail(GBS_E_ARG, "null Q or alpha");
+    const int n = 2 * M;
+    for (int i = 0; i < n * n; ++i)
+        if (!finite_z(Q[i])) return fail(GBS_E_NONFINITE, "non-finite Q entry %d", i);
+    for (int i = 0; i < n; ++i)
+        if (!finite_z(alpha[i])) return fail(GBS_E_NONFINITE, "non-finite alpha entry %d", i);
+    double qmax = 0.0;
+    for (int i = 0; i < n * n; ++i) qmax = std::max(qmax, std::hypot(Q[i].re, Q[i].im));
+    for (int i = 0; i < n; ++i)
+        for (int j = i; j < n; ++j) {
+            const gbs_z a = Q[i * n + j], b = Q[j * n + i];
+            if (std::hypot(a.re - b.re, a.im + b.im) > 1e-12 * std::max(1.0, qmax))
+                return fail(GBS_E_NOT_PD, "Q is not Hermitian at (%d, %d)", i, j);
+        }
+    double amax = 0.0;
+    for (int i = 0; i < n; ++i) amax = std::max(amax, std::hypot(alpha[i].re, alpha[i].im));
+    for (int i = 0; i < M; ++i) {
+        const gbs_z a = alpha[i], b = alpha[M + i];
+        if (std::hypot(a.re - b.re, a.im + b.im) > 1e-12 * std::max(1.0, amax))
+            return fail(GBS_E_ARG, "alpha is not of the form [a; conj(a)] at mode %d", i);
+    }
+    std::vector<cplx> L(n * n);
+    for (int i = 0; i < n * n; ++i) L[i] = cplx(Q[i].re, Q[i].im);
+    if (!cholesky(L, n)) return fail(GBS_E_NOT_PD, "Q is not positive definite");
+    // Q^-1 = L^-H L^-1, column by column
+    std::vector<cplx> Qi(n * n);
+    std::vector<cplx> col(n);
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < n; ++i) {
+            cplx s = (i == j) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) s -= L[i * n + k] * col[k];
+            col[i] = s / L[i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            cplx s = col[i];
+            for (int k = i + 1; k < n; ++k) s -= std::conj(L[k * n + i]) * col[k];
+            col[i] = s / L[i * n + i].real();
+        }
+        for (int i = 0; i < n; ++i) Qi[i * n + j] = col[i];
+    }
+    double logdet = 0.0;
+    for (int i = 0; i < n; ++i) logdet += 2.0 * std::log(L[i * n + i].real());
+    // A = X (I - Q^-1): rows of the two halves swapped
+    auto Aat = [&](int i, int j) {
+        const int xi = i < M ? i + M : i - M;
+        return ((xi == j) ? cplx(1.0) : cplx(0.0)) - Qi[xi * n + j];
+    };
+    double anorm = 0.0, offb = 0.0, diffb = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) anorm = std::max(anorm, std::abs(Aat(i, j)));
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) {
+            offb = std::max(offb, std::abs(Aat(i, M + j)));
+            offb = std::max(offb, std::abs(Aat(M + i, j)));
+            diffb = std::max(diffb, std::abs(Aat(M + i, M + j) - std::conj(Aat(i, j))));
+        }
+    if (offb > 1e-10 * std::max(1.0, anorm) || diffb > 1e-10 * std::max(1.0, anorm))
+        return fail(GBS_E_NOT_PURE, "A = X(I - Q^-1) is not B (+) conj(B) (off-block %.3g, mismatch %.3g)", offb, diffb);
+    std::vector<cplx> al(n);
+    for (int i = 0; i < n; ++i) al[i] = cplx(alpha[i].re, alpha[i].im);
+    std::vector<cplx> qa(n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) qa[i] += Qi[i * n + j] * al[j];
+    cplx quad = 0.0;
+    for (int i = 0; i < n; ++i) quad += std::conj(al[i]) * qa[i];
+    if (B_out)
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                const cplx b = Aat(i, j);
+                B_out[i * M + j] = gbs_z{b.real(), b.imag()};
+            }
+    if (gamma_out)
+        for (int i = 0; i < M; ++i) gamma_out[i] = gbs_z{qa[M + i].real(), qa[M + i].imag()};
+    if (p_vac_out) *p_vac_out = std::exp(-0.5 * quad.real() - 0.5 * logdet);
+    return GBS_OK;
+}
+
+gbs_status gbs_lhaf(const gbs_z* A, int32_t M, int64_t lda, const gbs_z* gamma, const int32_t* mult,
+                    gbs_precision prec, gbs_z* out, gbs_diag* diag) {
+    if (!out) return fail(GBS_E_ARG, "null output");
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    if (prec != GBS_FP64) return fail(GBS_E_UNSUPPORTED, "only GBS_FP64 is implemented");
+    std::vector<gbs_z> Aexp;
+    int32_t N = 0;
+    gbs_status st = expand_impl(A, M, lda, gamma, mult, Aexp, &N);
+    if (st != GBS_OK) return st;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    return lhaf_host_matrix(Aexp.data(), N, out, diag);
+}
+
+gbs_status gbs_haf(const gbs_z* A, int32_t N, int64_t lda, gbs_precision prec, gbs_z* out, gbs_diag* diag) {
+    if (!out) return fail(GBS_E_ARG, "null output");
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    if (prec != GBS_FP64) return fail(GBS_E_UNSUPPORTED, "only GBS_FP64 is implemented");
+    gbs_status st = check_matrix(A, N, lda, "A", true);
+    if (st != GBS_OK) return st;
+    if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d exceeds %d", N, GBS_MAX_DIM);
+    if (N & 1) {
+        out->re = 0.0;
+        out->im = 0.0;
+        if (diag) std::memset(diag, 0, sizeof *diag);
+        return GBS_OK;
+    }
+    std::vector<gbs_z> A0((size_t)N * N);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) A0[(size_t)i * N + j] = (i == j) ? gbs_z{0.0, 0.0} : A[(int64_t)i * lda + j];
+    std::lock_guard<std::mutex> lock(g_mutex);
+    return lhaf_host_matrix(A0.data(), N, out, diag);
+}
+
+gbs_status gbs_probability(const gbs_z* Q, const gbs_z* alpha, const int32_t* pattern, int32_t M,
+                           gbs_precision prec, double* p_out, gbs_z* lhaf_out, gbs_diag* diag) {
+    if (!p_out || (M > 0 && !pattern)) return fail(GBS_E_ARG, "null output or pattern");
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    if (prec != GBS_FP64) return fail(GBS_E_UNSUPPORTED, "only GBS_FP64 is implemented");
+    std::vector<gbs_z> B((size_t)M * M), gamma(M);
+    double pvac = 0.0;
+    gbs_status st = gbs_pure_state(Q, alpha, M, B.data(), gamma.data(), &pvac);
+    if (st != GBS_OK) return st;
+    std::vector<gbs_z> Aexp;
+    int32_t N = 0;
+    st = expand_impl(B.data(), M, M, gamma.data(), pattern, Aexp, &N);
+    if (st != GBS_OK) return st;
+    gbs_z lh{1.0, 0.0};
+    {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        st = lhaf_host_matrix(Aexp.data(), N, &lh, diag);
+    }
+    if (st != GBS_OK) return st;
+    double lfact = 0.0;
+    for (int i = 0; i < M; ++i) lfact += std::lgamma((double)pattern[i] + 1.0);
+    *p_out = pvac * (lh.re * lh.re + lh.im * lh.im) * std::exp(-lfact);
+    if (lhaf_out) *lhaf_out = lh;
+    return GBS_OK;
+}
+
+gbs_status gbs_lhaf_terms(const gbs_z* A, int32_t N, int64_t lda, const uint64_t* masks, int64_t count,
+                          gbs_precision prec, gbs_z* terms_out) {
+    if (count < 0 || (count > 0 && (!masks || !terms_out))) return fail(GBS_E_ARG, "bad mask list");
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    if (prec != GBS_FP64) return fail(GBS_E_UNSUPPORTED, "only GBS_FP64 is implemented");
+    gbs_status st = check_matrix(A, N, lda, "A", true);
+    if (st != GBS_OK) return st;
+    if (N < 1) return fail(GBS_E_ARG, "terms need N >= 1");
+    if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d exceeds %d", N, GBS_MAX_DIM);
+    const int Np = N + (N & 1), n = Np / 2;
+    for (int64_t j = 0; j < count; ++j)
+        if (n < 64 && (masks[j] >> n) != 0) return fail(GBS_E_ARG, "mask %lld has bits beyond n = %d", (long long)j, n);
+    std::lock_guard<std::mutex> lock(g_mutex);
+    DevCtx* c = nullptr;
+    st = current_ctx(&c);
+    if (st != GBS_OK) return st;
+    std::vector<gbs_z> Ah((size_t)N * N);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) Ah[(size_t)i * N + j] = A[(int64_t)i * lda + j];
+    HIP_TRY(hipStreamWaitEvent(c->stream, c->done, 0));
+    HIP_TRY(hipMemcpyAsync(c->Ain, Ah.data(), sizeof(gbs_z) * Ah.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(gbs::launch_prep(c->Ain, N, N, Np, c->A0, c->dvec, c->stream));
+    const int D = n + 1;
+    for (int s = 0; s <= n; ++s) {
+        std::vector<int64_t> pos;
+        std::vector<uint64_t> grp;
+        for (int64_t j = 0; j < count; ++j)
+            if (__builtin_popcountll(masks[j]) == s) {
+                pos.push_back(j);
+                grp.push_back(masks[j]);
+            }
+        if (grp.empty()) continue;
+        if (s == 0) {  // the empty subset contributes [eta^n] exp(0) = 0 for n >= 1
+            for (int64_t j : pos) terms_out[j] = gbs_z{0.0, 0.0};
+            continue;
+        }
+        for (size_t off = 0; off < grp.size(); off += kChunk) {
+            const size_t len = std::min<size_t>(kChunk, grp.size() - off);
+            st = ensure_buffer((void**)&c->masks, &c->masks_cap, len, sizeof(uint64_t));
+            if (st != GBS_OK) return st;
+            if (c->terms) hipFree(c->terms);
+            c->terms = nullptr;
+            HIP_TRY(hipMalloc((void**)&c->terms, sizeof(double2) * len));
+            st = ensure_buffer((void**)&c->E, &c->E_cap, len * 2 * (D + 1), sizeof(double2));
+            if (st != GBS_OK) return st;
+            const size_t nblk = (len + 64 * kPerThread - 1) / (64 * kPerThread);
+            st = ensure_buffer((void**)&c->partials, &c->partials_cap, nblk * 5, sizeof(double));
+            if (st != GBS_OK) return st;
+            HIP_TRY(hipMemcpyAsync(c->masks, grp.data() + off, sizeof(uint64_t) * len, hipMemcpyHostToDevice, c->stream));
+            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, c->E};
+            HIP_TRY(gbs::launch_charpoly(p1, c->stream));
+            gbs::LaunchPhase2 p2{c->E, len, D, ((n - s) & 1) ? -1.0 : 1.0, kPerThread, c->partials, c->terms};
+            HIP_TRY(gbs::launch_series(n, p2, c->stream));
+            std::vector<double2> th(len);
+            HIP_TRY(hipMemcpyAsync(th.data(), c->terms, sizeof(double2) * len, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            for (size_t q = 0; q < len; ++q) terms_out[pos[off + q]] = gbs_z{th[q].x, th[q].y};
+        }
+    }
+    HIP_TRY(hipEventRecord(c->done, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return GBS_OK;
+}
+
+gbs_status gbs_lhaf_device(const gbs_z* A_dev, int32_t N, gbs_precision prec, gbs_z* out_dev, double* abs_sum_dev,
+                           void* stream) {
+    if (N < 0 || (N > 0 && !A_dev) || !out_dev) return fail(GBS_E_ARG, "bad device arguments");
+    if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d exceeds %d", N, GBS_MAX_DIM);
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    if (prec != GBS_FP64) return fail(GBS_E_UNSUPPORTED, "only GBS_FP64 is implemented");
+    std::lock_guard<std::mutex> lock(g_mutex);
+    DevCtx* c = nullptr;
+    gbs_status st = current_ctx(&c);
+    if (st != GBS_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int Np = N + (N & 1);
+    HIP_TRY(hipStreamWaitEvent(s, c->done, 0));
+    if (Np > 0)
+        HIP_TRY(gbs::launch_prep(reinterpret_cast<const double2*>(A_dev), N, N, Np, c->A0, c->dvec, s));
+    st = run_sum(c, Np, s, reinterpret_cast<double2*>(out_dev), abs_sum_dev, nullptr);
+    if (st != GBS_OK) return st;
+    HIP_TRY(hipEventRecord(c->done, s));
+    return GBS_OK;
+}
+
+gbs_status gbs_profile_enable(int on) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    for (auto& r : g_prof_recs) {
+        hipEventSynchronize(r.b);
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_prof_recs.clear();
+    g_prof = on != 0;
+    return GBS_OK;
+}
+
+gbs_status gbs_profile_read(gbs_profile* out) {
+    if (!out) return fail(GBS_E_ARG, "null output");
+    std::lock_guard<std::mutex> lock(g_mutex);
+    gbs_profile p{};
+    for (auto& r : g_prof_recs) {
+        HIP_TRY(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        if (r.kind == kProfCharpoly) {
+            p.charpoly_ms += ms;
+            p.charpoly_launches += 1;
+            p.charpoly_flops += r.flops;
+            p.subset_terms += r.subsets;
+        } else if (r.kind == kProfSeries) {
+            p.series_ms += ms;
+            p.series_launches += 1;
+        } else {
+            p.reduce_ms += ms;
+            p.reduce_launches += 1;
+        }
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_prof_recs.clear();
+    *out = p;
+    return GBS_OK;
+}
+
+double gbs_yardstick_flops(int32_t N) {
+    if (N < 0 || N > GBS_MAX_DIM) return 0.0;
+    const int n = (N + 1) / 2;
+    double f = 0.0;
+    for (int s = 1; s <= n; ++s) f += (double)binom_host(n, s) * subset_flops(n, s);
+    return f;
+}
+
+gbs_status gbs_selftest(int32_t* failures) {
+    if (!failures) return fail(GBS_E_ARG, "null output");
+    std::lock_guard<std::mutex> lock(g_mutex);
+    DevCtx* c = nullptr;
+    gbs_status st = current_ctx(&c);
+    if (st != GBS_OK) return st;
+    double hin[64], hout[256];
+    for (int l = 0; l < 64; ++l) hin[l] = std::ldexp(1.0, l % 20) + 0.25 * l;
+    double *din = nullptr, *dout = nullptr;
+    HIP_TRY(hipMalloc((void**)&din, sizeof hin));
+    HIP_TRY(hipMalloc((void**)&dout, sizeof hout));
+    HIP_TRY(hipMemcpy(din, hin, sizeof hin, hipMemcpyHostToDevice));
+    HIP_TRY(gbs::launch_selftest(din, dout, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(hout, dout, sizeof hout, hipMemcpyDeviceToHost));
+    hipFree(din);
+    hipFree(dout);
+    int bad = 0;
+    for (int l = 0; l < 64; ++l) {
+        double so = 0.0, ss = 0.0;
+        for (int q = 0; q < 8; ++q) so += hin[(l & ~7) + q];
+        for (int q = 0; q < 8; ++q) ss += hin[(l & 7) + 8 * q];
+        if (std::fabs(hout[l] - so) > 1e-12 * std::fabs(so)) ++bad;
+        if (std::fabs(hout[64 + l] - ss) > 1e-12 * std::fabs(ss)) ++bad;
+        if (hout[128 + l] != hin[37]) ++bad;
+        if (l >= 1 && hout[192 + l] != hin[l - 1]) ++bad;
+    }
+    *failures = bad;
+    return GBS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+"""C-ABI library: loading, exported symbols and host-only logic (no GPU).
+
+Host logic tested here: pattern expansion, the pure-state parameters of Q
+(Cholesky on the host) and argument validation.  Each is compared with the
+oracle's independent numpy implementation or with fixed error codes.
+"""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2010_15595_amd as gbs
+from paper_2010_15595_amd import _lib, workloads
+
+HEADER = _lib.os.path.join(_lib.os.path.dirname(_lib.HERE), "include", "gbs_lhaf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gbs_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    names = declared_functions()
+    assert "gbs_lhaf" in names and "gbs_lhaf_device" in names and "gbs_probability" in names
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in gbs_lhaf.h but not exported"
+
+
+def test_status_strings():
+    L = gbs.lib()
+    for code in range(-9, 1):
+        assert L.gbs_status_string(code)
+    assert L.gbs_status_string(0) == b"ok"
+
+
+def test_max_dim():
+    assert gbs.max_dim() == 64
+
+
+def test_no_device_reports_device_error():
+    rc = gbs.lib().gbs_init(0)
+    if rc == 0:
+        pytest.skip("a GPU is visible: the device-less path does not apply")
+    assert rc == -7
+    assert b"device" in gbs.lib().gbs_last_error()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_expand_matches_oracle(seed):
+    st = workloads.pure_state(9, 0.6, 0.3, seed=seed)
+    r = np.random.default_rng(seed)
+    pat = r.integers(0, 4, 9).astype(np.int32)
+    got = gbs.expand(st["B"], st["gamma"], pat)
+    ref = oracle.expand(st["B"], st["gamma"], pat)
+    assert got.shape == ref.shape
+    assert np.array_equal(got, ref)
+    got2 = gbs.expand(st["B"], None, pat)
+    assert np.array_equal(got2, oracle.expand(st["B"], None, pat))
+
+
+def test_expand_config2_dimension():
+    st = workloads.config2()
+    got = gbs.expand(st["B"], st["gamma"], st["pattern"])
+    assert got.shape == (32, 32)
+    assert np.array_equal(got, oracle.expand(st["B"], st["gamma"], st["pattern"]))
+
+
+@pytest.mark.parametrize("M,r,sigma", [(1, 0.5, 0.2), (4, 0.9, 0.3), (16, 1.0, 0.3), (40, 1.2, 0.1)])
+def test_pure_state_matches_oracle(M, r, sigma):
+    st = workloads.pure_state(M, r, sigma, seed=M)
+    B, g, pv = gbs.pure_state(st["Q"], st["alpha_vec"])
+    Bo, go, pvo = oracle.pure_state_params(st["Q"], st["alpha_vec"])
+    assert np.max(np.abs(B - Bo)) <= 1e-11
+    assert np.max(np.abs(g - go)) <= 1e-11
+    assert pv == pytest.approx(pvo, rel=1e-11)
+
+
+def _expect(code, fn, *args):
+    with pytest.raises(gbs.GbsError) as ei:
+        fn(*args)
+    assert ei.value.code == code, str(ei.value)
+
+
+def test_validation_errors_before_any_device_work():
+    A = workloads.random_normal_symmetric(6, seed=3)
+    bad = A.copy()
+    bad[0, 1] += 1.0
+    _expect(-2, gbs.lhaf, bad)
+    nan = A.copy()
+    nan[2, 2] = np.nan
+    _expect(-3, gbs.lhaf, nan)
+    _expect(-4, gbs.lhaf, A, None, [20, 20, 20, 20, 0, 0])
+    _expect(-1, gbs.lhaf, A, None, [1, -1, 1, 1, 1, 1])
+    _expect(-9, gbs.lhaf, A, None, None, gbs.GBS_FP32_COMP)
+    _expect(-2, gbs.haf, bad)
+    _expect(-1, gbs.lhaf_terms, A, [1 << 5])
+    L = gbs.lib()
+    assert L.gbs_lhaf(None, 3, 3, None, None, 0, None, None) == -1
+    assert L.gbs_expand(None, 2, 2, None, None, None, 0, None) == -1
+    assert L.gbs_lhaf(None, 3, 3, None, None, 7, ctypes.byref(_lib.gbs_z()), None) == -1
+
+
+def test_pure_state_validation():
+    st = workloads.pure_state(3, 0.5, 0.2, seed=5)
+    Q = st["Q"].copy()
+    Q[0, 1] += 0.3  # not Hermitian
+    _expect(-6, gbs.pure_state, Q, st["alpha_vec"])
+    # mixed state: thermal noise on top of a pure state
+    Qm = st["Q"] + 0.2 * np.eye(6)
+    _expect(-5, gbs.pure_state, Qm, st["alpha_vec"])
+    al = st["alpha_vec"].copy()
+    al[4] = 5.0  # not [a; conj(a)]
+    _expect(-1, gbs.pure_state, st["Q"], al)
+    _expect(-6, gbs.pure_state, -np.eye(6, dtype=complex), np.zeros(6))
+
+
+def test_yardstick_flops_formula():
+    """sum_s C(n,s) [(40/3 + 4/3) m^3 + 8 min(n-1, m-1) m^2], m = 2s."""
+    from math import comb
+
+    for N in (16, 32, 50):
+        n = N // 2
+        ref = sum(comb(n, s) * ((44 / 3) * (2 * s) ** 3 + 8 * min(n - 1, 2 * s - 1) * (2 * s) ** 2) for s in range(1, n + 1))
+        assert gbs.yardstick_flops(N) == pytest.approx(ref, rel=1e-12)
+    assert gbs.yardstick_flops(50) == pytest.approx(1.260e13, rel=1e-3)

@@ -1,0 +1,257 @@
+"""GPU parity: the HIP loop-hafnian path (through the C ABI) against the CPU
+oracle, on seeded inputs of the workload shapes.
+
+Tolerance (FP64; reading R6 of the design notes): the exact value is unique, so
+results are compared to the long-double oracle with
+    |gpu - ref| <= max(1e-10 |ref|, 2e-14 * sum_S |t_S|)
+(the second, normwise form is the rounding bound of a signed sum of 2^n
+terms, each with ~1e-16 relative error; it governs wherever the cancellation
+ratio sum|t_S| / |lhaf| exceeds ~1e3).  Full-size (N = 40, 50) checks use
+sampled subset terms compared one by one, plus closed forms that hold at any
+size.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_15595_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-10
+NORMWISE = 2e-14
+
+
+@pytest.fixture(scope="module")
+def gbs():
+    import paper_2010_15595_amd as g
+
+    g.init(0)
+    return g
+
+
+def close(got, ref, abs_sum, rel=REL, normwise=NORMWISE):
+    err = abs(complex(got) - complex(ref))
+    tol = max(rel * abs(ref), normwise * abs_sum)
+    return err <= tol, err, tol
+
+
+def report(tag, got, ref, abs_sum):
+    ok, err, tol = close(got, ref, abs_sum)
+    kappa = abs_sum / max(abs(ref), 1e-300)
+    print(f"[{tag}] ref={complex(ref):.10e} gpu={complex(got):.10e} |err|={err:.2e} tol={tol:.2e} "
+          f"rel={err / max(abs(ref), 1e-300):.2e} kappa={kappa:.2e}", flush=True)
+    return ok
+
+
+def test_cross_lane_selftest(gbs):
+    assert gbs.selftest() == 0
+
+
+def test_config1_n16_against_definition(gbs):
+    st = workloads.config1()
+    val, d = gbs.lhaf(st["B"], st["gamma"], st["pattern"], with_diag=True)
+    A = oracle.expand(st["B"], st["gamma"], st["pattern"])
+    ref = oracle.to_complex(oracle.lhaf_dp(A, prec="ld"))
+    assert report("C1 N=16 vs dp", val, ref, d["abs_sum"])
+    # C1 is well conditioned: the 1e-10 relative target holds outright
+    assert abs(val - ref) <= 1e-10 * abs(ref)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 15, 16, 17, 20, 23, 24])
+def test_random_normal_sizes(gbs, N):
+    A = workloads.random_normal_symmetric(N, seed=10 + N, scale=0.5)
+    val, d = gbs.lhaf(A, with_diag=True)
+    ref, ab = oracle.lhaf_pt(A, prec="ld", with_abs=True)
+    assert report(f"normal N={N}", val, oracle.to_complex(ref), d["abs_sum"])
+    assert d["abs_sum"] == pytest.approx(float(ab), rel=1e-9)
+
+
+@pytest.mark.parametrize("N", [18, 22, 26])
+def test_uniform_random_inputs(gbs, N):
+    """The paper's timing inputs: Re, Im ~ U[0,1), symmetrised."""
+    A = workloads.random_uniform_symmetric(N, seed=N)
+    val, d = gbs.lhaf(A, with_diag=True)
+    ref = oracle.to_complex(oracle.lhaf_pt(A, prec="ld"))
+    assert report(f"uniform N={N}", val, ref, d["abs_sum"])
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 10])
+def test_haf_double_factorial(gbs, n):
+    A = np.ones((2 * n, 2 * n), dtype=complex)
+    val, d = gbs.haf(A, with_diag=True)
+    assert report(f"haf 1_{2 * n}", val, oracle.double_factorial(2 * n - 1), d["abs_sum"])
+
+
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_haf_bipartite_permanent(gbs, n):
+    r = np.random.default_rng(50 + n)
+    B = r.integers(-3, 4, (n, n)) + 1j * r.integers(-3, 4, (n, n))
+    A = np.zeros((2 * n, 2 * n), dtype=complex)
+    A[:n, n:] = B
+    A[n:, :n] = B.T
+    val, d = gbs.haf(A, with_diag=True)
+    assert report(f"perm n={n}", val, oracle.ryser_permanent(B.tolist()), d["abs_sum"])
+
+
+def test_haf_odd_is_zero(gbs):
+    assert gbs.haf(np.ones((5, 5), dtype=complex)) == 0
+
+
+@pytest.mark.parametrize("n", [1, 2, 6, 11, 16, 21, 26, 30])
+def test_telephone_numbers(gbs, n):
+    val, d = gbs.lhaf(np.ones((n, n), dtype=complex), with_diag=True)
+    assert report(f"T({n})", val, oracle.telephone(n), d["abs_sum"])
+
+
+def test_edge_cases(gbs):
+    assert gbs.lhaf(np.zeros((0, 0), dtype=complex)) == 1
+    a = np.array([[0.3 - 0.7j]])
+    assert gbs.lhaf(a) == pytest.approx(0.3 - 0.7j, rel=1e-15)
+    A2 = np.array([[0.5 + 0.1j, -0.2 + 0.3j], [-0.2 + 0.3j, 1.5 - 0.4j]])
+    assert gbs.lhaf(A2) == pytest.approx(A2[0, 0] * A2[1, 1] + A2[0, 1], rel=1e-14)
+    assert gbs.lhaf(np.zeros((7, 7), dtype=complex)) == 0
+    dg = np.diag(np.arange(1, 9) * (0.5 + 0.25j))
+    assert gbs.lhaf(dg) == pytest.approx(np.prod(np.diag(dg)), rel=1e-13)
+    st = workloads.pure_state(4, 0.5, 0.2, seed=1)
+    assert gbs.lhaf(st["B"], st["gamma"], [0, 0, 0, 0]) == 1
+
+
+@pytest.mark.parametrize("pattern", [[3, 0, 2, 1], [5, 0, 0, 0], [1, 1, 1, 4], [2, 2, 2, 2, 2, 2, 2, 2, 2]])
+def test_repeated_modes(gbs, pattern):
+    M = len(pattern)
+    st = workloads.pure_state(M, 0.8, 0.3, seed=M + sum(pattern))
+    val, d = gbs.lhaf(st["B"], st["gamma"], pattern, with_diag=True)
+    A = oracle.expand(st["B"], st["gamma"], pattern)
+    ref = oracle.to_complex(oracle.lhaf_pt(A, prec="ld"))
+    assert report(f"pattern {pattern}", val, ref, d["abs_sum"])
+
+
+def test_config2_n32_full_sum(gbs):
+    st = workloads.config2()
+    val, d = gbs.lhaf(st["B"], st["gamma"], st["pattern"], with_diag=True)
+    A = oracle.expand(st["B"], st["gamma"], st["pattern"])
+    ref, ab = oracle.lhaf_pt(A, prec="ld", with_abs=True)
+    assert report("C2 N=32", val, oracle.to_complex(ref), d["abs_sum"])
+
+
+def test_config2_probability(gbs):
+    st = workloads.config2()
+    p, lh = gbs.probability(st["Q"], st["alpha_vec"], st["pattern"], with_lhaf=True)
+    p_ref, lh_ref = oracle.probability(st["Q"], st["alpha_vec"], st["pattern"], prec="ld")
+    print(f"[C2 probability] gpu={p:.10e} oracle={p_ref:.10e} rel={abs(p - p_ref) / p_ref:.2e}", flush=True)
+    assert abs(p - p_ref) <= 1e-6 * p_ref  # |lhaf|^2 doubles the lhaf error; kappa ~ 1e6 here
+
+
+def test_probability_small_states(gbs):
+    st = workloads.pure_state(5, 0.6, 0.3, seed=4)
+    for pat in ([0, 0, 0, 0, 0], [1, 0, 0, 0, 0], [2, 1, 0, 1, 3], [1, 1, 1, 1, 1]):
+        p = gbs.probability(st["Q"], st["alpha_vec"], pat)
+        p_ref, _ = oracle.probability(st["Q"], st["alpha_vec"], pat, prec="ld")
+        assert p == pytest.approx(p_ref, rel=1e-10, abs=1e-300)
+
+
+def _sample_masks(n, per_class, seed):
+    r = np.random.default_rng(seed)
+    masks = []
+    for s in range(1, n + 1):
+        total = math.comb(n, s)
+        for _ in range(min(per_class, total)):
+            bits = r.choice(n, size=s, replace=False)
+            masks.append(int(sum(1 << int(b) for b in bits)))
+    return np.array(sorted(set(masks)), dtype=np.uint64)
+
+
+@pytest.mark.parametrize("N", [40, 50])
+def test_sampled_subset_terms_full_size(gbs, N):
+    """Full-size workload (M = 100, r = 1.2): individual subset terms from every
+    size class, GPU vs oracle one by one."""
+    st = workloads.config3(N)
+    A = oracle.expand(st["B"], st["gamma"], st["pattern"])
+    masks = _sample_masks(N // 2, 6, seed=N)
+    got = gbs.lhaf_terms(A, masks)
+    ref = oracle.terms(A, masks, prec="ld")
+    scale = np.abs(ref)
+    err = np.abs(got - ref)
+    worst = np.max(err / np.maximum(scale, 1e-300))
+    print(f"[terms N={N}] {len(masks)} subsets, worst rel err {worst:.2e}, median {np.median(err / scale):.2e}",
+          flush=True)
+    assert worst <= 1e-9
+
+
+def test_n50_block_diagonal_product(gbs):
+    """lhaf of a permuted block-diagonal 50 x 50 matrix = product of its five
+    10 x 10 blocks' loop hafnians (brute force): a full-size pin."""
+    blocks = [workloads.random_normal_symmetric(10, seed=900 + k, scale=0.6) for k in range(5)]
+    A = np.zeros((50, 50), dtype=complex)
+    for k, Bk in enumerate(blocks):
+        A[10 * k:10 * k + 10, 10 * k:10 * k + 10] = Bk
+    p = np.random.default_rng(77).permutation(50)
+    A = A[np.ix_(p, p)]
+    expect = np.prod([oracle.to_complex(oracle.lhaf_dp(Bk, prec="ld")) for Bk in blocks])
+    val, d = gbs.lhaf(A, with_diag=True)
+    assert report("N=50 block product", val, expect, d["abs_sum"])
+
+
+def _single_mode(N, b, g):
+    import mpmath
+
+    with mpmath.workdps(50):
+        b = mpmath.mpc(b.real, b.imag)
+        g = mpmath.mpc(g.real, g.imag)
+        tot = mpmath.mpc(0)
+        for k in range(N // 2 + 1):
+            tot += mpmath.factorial(N) / (mpmath.factorial(k) * mpmath.factorial(N - 2 * k) * 2**k) * b**k * g ** (N - 2 * k)
+        return complex(tot)
+
+
+@pytest.mark.parametrize("N", [33, 50])
+def test_single_mode_repeated_closed_form(gbs, N):
+    """One mode with multiplicity N: sum_k N!/(k!(N-2k)!2^k) b^k g^(N-2k)."""
+    b, g = 0.31 - 0.12j, 0.2 + 0.45j
+    val, d = gbs.lhaf(np.array([[b]]), np.array([g]), [N], with_diag=True)
+    assert report(f"single mode x{N}", val, _single_mode(N, b, g), d["abs_sum"])
+
+
+def test_rank_one_n50(gbs):
+    v = np.exp(1j * np.linspace(0, 2, 50)) * 0.9
+    A = np.outer(v, v)
+    np.fill_diagonal(A, v)
+    val, d = gbs.lhaf(A, with_diag=True)
+    assert report("rank one N=50", val, oracle.telephone(50) * np.prod(v), d["abs_sum"])
+
+
+def test_bitwise_determinism_and_device_path(gbs):
+    import torch
+
+    st = workloads.config3(40)
+    A = oracle.expand(st["B"], st["gamma"], st["pattern"])
+    v1 = gbs.lhaf(A)
+    v2 = gbs.lhaf(A)
+    assert v1 == v2
+    At = torch.from_numpy(A).to("cuda:0")
+    out = torch.zeros(1, dtype=torch.complex128, device="cuda:0")
+    ab = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    gbs.lhaf_device(At, out, ab)
+    torch.cuda.synchronize()
+    assert complex(out.cpu().numpy()[0]) == v1
+    assert float(ab.cpu().numpy()[0]) > abs(v1)
+
+
+def test_allones_accuracy_report(gbs):
+    """Fig. 2 experiment: relative error of lhaf(1_n) vs T(n), printed next to
+    the paper's long-double numbers (context), bounded by the normwise gate."""
+    paper = {}
+    for line in open(__file__.replace("test_gpu_parity.py", "golden/fig2_allones_relerr.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            paper[int(k)] = float(v)
+    for n in (30, 34, 38, 42):
+        val, d = gbs.lhaf(np.ones((n, n), dtype=complex), with_diag=True)
+        T = oracle.telephone(n)
+        rel = abs(val - T) / T
+        print(f"[Fig.2 n={n}] fp64 gpu rel err {rel:.2e} (paper, long double: {paper[n]:.2e}); "
+              f"kappa {d['kappa']:.2e}", flush=True)
+        assert abs(val - T) <= NORMWISE * d["abs_sum"]
