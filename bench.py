@@ -76,7 +76,19 @@ def main():
     ap.add_argument("--N", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 3 x 268435456 bytes")
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the subset sum would shard by "
@@ -135,7 +147,7 @@ def main():
     gpu_ms = ev0.elapsed_time(ev1)
     val = complex(out.cpu().numpy()[0])
     abs_sum = float(ab.cpu().numpy()[0])
-    if val != ref_val:
+    if args.warmup > 0 and val != ref_val:
         log("WARNING: result changed between steps (non-deterministic)")
     sec = gpu_ms / 1000.0
     lhaf_per_s = args.steps / sec

@@ -266,15 +266,24 @@ __device__ __forceinline__ void labudde_step(int rho, int m, int D, int lane, do
     wave_sync();
     if (lane <= D) {
         const double2* prev = L.ring + ((r + 1) % RS) * RS;
-        double2 e = prev[lane];
-        if (lane >= 1) e = cfms(hrr, prev[lane - 1], e);
+        double2 e0 = prev[lane];
+        double2 e1 = cz();
+        if (lane >= 1) e0 = cfms(hrr, prev[lane - 1], e0);
+        // uniform trip count (K), two independent accumulators; lane d only
+        // takes terms with k < d (coefficient index d - k - 1 >= 0)
         int slot = (r + 2) % RS;
-        const int kmax = min(K, lane - 1);
-        for (int k = 1; k <= kmax; ++k) {
-            e = cfms(L.betab[k], L.ring[slot * RS + lane - k - 1], e);
-            slot = (slot + 1 == RS) ? 0 : slot + 1;
+        int k = 1;
+        for (; k + 1 <= K; k += 2) {
+            const int s1 = (slot + 1 == RS) ? 0 : slot + 1;
+            const double2 b0 = L.betab[k], b1 = L.betab[k + 1];
+            const double2 q0 = L.ring[slot * RS + max(lane - k - 1, 0)];
+            const double2 q1 = L.ring[s1 * RS + max(lane - k - 2, 0)];
+            if (k < lane) e0 = cfms(b0, q0, e0);
+            if (k + 1 < lane) e1 = cfms(b1, q1, e1);
+            slot = (s1 + 1 == RS) ? 0 : s1 + 1;
         }
-        L.ring[(r % RS) * RS + lane] = e;
+        if (k <= K && k < lane) e0 = cfms(L.betab[k], L.ring[slot * RS + lane - k - 1], e0);
+        L.ring[(r % RS) * RS + lane] = cadd(e0, e1);
     }
     wave_sync();
 }
