@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--N", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the lane-grid autotuner (use the heuristic or GBS_AUTOTUNE_CACHE)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -124,6 +126,12 @@ def main():
     ab = torch.zeros(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
 
+    tuned = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        rep = gbs.autotune(n)
+        tuned = {s: lay for s, (lay, _) in rep.items()}
+        log(f"autotune n={n} ({time.perf_counter() - t0:.2f} s): " + " ".join(f"{s}:{lay}" for s, lay in tuned.items()))
     log(f"warmup {args.warmup} step(s), N={N} ({int(terms)} subsets/step) ...")
     for _ in range(args.warmup):
         gbs.lhaf_device(A_dev, out, ab, stream)
@@ -175,13 +183,14 @@ def main():
                         f"{N} distinct modes occupied",
             "N": N,
             "subset_terms_per_lhaf": int(terms),
+            "lane_grid_per_subset_size": tuned,
         },
         "subset_terms_per_s": terms * lhaf_per_s,
         "yardstick_flops_per_lhaf": flops,
         "pct_fp64_peak": 100.0 * flops * lhaf_per_s / (FP64_PEAK_TFLOPS * 1e12),
         "roofline": {
             "bound": "alu",
-            "kernel": "charpoly_kernel (gather + Householder Hessenberg + La Budde, one wavefront per subset)",
+            "kernel": "charpoly_kernel<P,Q,MR,MC> (gather + Householder Hessenberg + La Budde; 1, 2 or 4 subsets per wavefront)",
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",

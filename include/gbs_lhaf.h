@@ -140,6 +140,36 @@ gbs_status gbs_lhaf_terms(const gbs_z *A, int32_t N, int64_t lda, const uint64_t
 gbs_status gbs_lhaf_device(const gbs_z *A_dev, int32_t N, gbs_precision prec, gbs_z *out_dev,
                            double *abs_sum_dev, void *stream);
 
+/* ---- kernel layout selection and autotuning ------------------------------ */
+
+/* Lane grid of the per-subset kernel (rows x columns of lanes per subset). */
+typedef enum {
+    GBS_LAYOUT_DEFAULT = -1, /* heuristic, or the autotuned choice when one exists */
+    GBS_LAYOUT_4x4 = 0,      /* 16 lanes per subset, 4 subsets per wavefront, m <= 24 */
+    GBS_LAYOUT_8x4 = 1,      /* 32 lanes per subset, 2 subsets per wavefront, m <= 40 */
+    GBS_LAYOUT_8x8 = 2       /* 64 lanes per subset, m <= 64                          */
+} gbs_layout;
+
+/* Use `layout` for subsets of size s (m = 2s vertices) whenever the loop
+ * hafnian has n pairs; n = 0 applies to every n, s = 0 to every size the
+ * grid can hold (other sizes keep their setting).  GBS_LAYOUT_DEFAULT clears
+ * the setting.  GBS_E_ARG if s > 0 and the grid cannot hold m x m.  Affects
+ * the current device. */
+gbs_status gbs_set_layout(int32_t n, int32_t s, int32_t layout);
+
+typedef struct {
+    int32_t n;
+    int32_t layout[33];           /* chosen grid per subset size s = 1..n    */
+    double ns_per_subset[33][3];  /* measured time per subset, 0 = not valid */
+} gbs_tune_report;
+
+/* Project autotuner: for every subset size s of an n-pair loop hafnian, times
+ * each valid lane grid on a sample of that size class (HIP events, synthetic
+ * matrix; the work is data-independent) and keeps the fastest for the current
+ * device.  With GBS_AUTOTUNE_CACHE=<path> in the environment the choices are
+ * appended to / read from that file.  report may be NULL. */
+gbs_status gbs_autotune(int32_t n, gbs_tune_report *report);
+
 /* ---- diagnostics --------------------------------------------------------- */
 
 /* Per-kernel timing of the subset-sum kernels, measured with HIP events

@@ -9,6 +9,7 @@ from ._lib import (  # noqa: F401
     GBS_FP32_COMP,
     GBS_FP64,
     GbsError,
+    autotune,
     expand,
     finalize,
     haf,
@@ -23,5 +24,6 @@ from ._lib import (  # noqa: F401
     profile_read,
     pure_state,
     selftest,
+    set_layout,
     yardstick_flops,
 )

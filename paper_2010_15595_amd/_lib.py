@@ -37,6 +37,13 @@ class gbs_diag(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("n_pairs", ctypes.c_int32), ("launches", ctypes.c_int32)]
 
 
+class gbs_tune_report(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("layout", ctypes.c_int32 * 33), ("ns_per_subset", (ctypes.c_double * 3) * 33)]
+
+
+LAYOUTS = {0: "4x4", 1: "8x4", 2: "8x8"}
+
+
 class gbs_profile(ctypes.Structure):
     _fields_ = [("charpoly_ms", ctypes.c_double), ("series_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double),
                 ("charpoly_launches", ctypes.c_int64), ("series_launches", ctypes.c_int64),
@@ -100,6 +107,10 @@ def lib():
         L.gbs_profile_enable.restype = st
         L.gbs_profile_read.argtypes = [ctypes.POINTER(gbs_profile)]
         L.gbs_profile_read.restype = st
+        L.gbs_set_layout.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.gbs_set_layout.restype = st
+        L.gbs_autotune.argtypes = [ctypes.c_int32, ctypes.POINTER(gbs_tune_report)]
+        L.gbs_autotune.restype = st
         L.gbs_yardstick_flops.argtypes = [ctypes.c_int32]
         L.gbs_yardstick_flops.restype = ctypes.c_double
         _L = L
@@ -245,3 +256,20 @@ def profile_read():
 
 def yardstick_flops(N):
     return lib().gbs_yardstick_flops(int(N))
+
+
+def set_layout(n, s, layout):
+    """Force the per-subset kernel lane grid (0 = 4x4, 1 = 8x4, 2 = 8x8, -1 =
+    default) for size-s subsets of n-pair loop hafnians (0 = all)."""
+    _check(lib().gbs_set_layout(int(n), int(s), int(layout)))
+
+
+def autotune(n):
+    """Run the autotuner for n pairs; returns {s: (layout, {layout: ns/subset})}."""
+    r = gbs_tune_report()
+    _check(lib().gbs_autotune(int(n), ctypes.byref(r)))
+    out = {}
+    for s in range(1, n + 1):
+        times = {LAYOUTS[k]: r.ns_per_subset[s][k] for k in range(3) if r.ns_per_subset[s][k] > 0}
+        out[s] = (LAYOUTS[r.layout[s]], times)
+    return out

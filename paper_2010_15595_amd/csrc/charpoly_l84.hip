@@ -1,0 +1,37 @@
+// Per-subset kernel instantiations for the 8 x 4 lanes per subset, two subsets per wavefront; MR = ceil(m / 8), MC = ceil(m / 4).
+#include "lhaf_device.h"
+
+namespace gbs {
+
+template <int P, int Q, int MR, int MC>
+static hipError_t launch_charpoly_t(const LaunchPhase1& p, hipStream_t st) {
+    constexpr int G = P * Q;
+    constexpr int W = 64 / G;
+    const int T = (G >= p.D + 1) ? G : 64;
+    const size_t lds = sizeof(double2) * lds_doubles2(W, 64 / T, p.D);
+    const unsigned grid = (unsigned)((p.count + W - 1) / W);
+    hipLaunchKernelGGL((charpoly_kernel<P, Q, MR, MC>), dim3(grid), dim3(64), lds, st, p.A0, p.dvec, p.Np, p.s,
+                       p.rank0, p.count, p.masks, p.binom, p.D, T, p.Eout);
+    return hipGetLastError();
+}
+
+hipError_t launch_charpoly_l84(const LaunchPhase1& p, hipStream_t st) {
+    const int m = 2 * p.s;
+    const int mr = (m + 7) / 8, mc = (m + 3) / 4;
+    switch (mc) {
+        case 1: return launch_charpoly_t<8, 4, 1, 1>(p, st);
+        case 2: return launch_charpoly_t<8, 4, 1, 2>(p, st);
+        case 3: return launch_charpoly_t<8, 4, 2, 3>(p, st);
+        case 4: return launch_charpoly_t<8, 4, 2, 4>(p, st);
+        case 5: return launch_charpoly_t<8, 4, 3, 5>(p, st);
+        case 6: return launch_charpoly_t<8, 4, 3, 6>(p, st);
+        case 7: return launch_charpoly_t<8, 4, 4, 7>(p, st);
+        case 8: return launch_charpoly_t<8, 4, 4, 8>(p, st);
+        case 9: return launch_charpoly_t<8, 4, 5, 9>(p, st);
+        case 10: return launch_charpoly_t<8, 4, 5, 10>(p, st);
+    }
+    (void)mr;
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gbs

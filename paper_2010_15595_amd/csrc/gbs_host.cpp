@@ -11,6 +11,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -72,7 +73,25 @@ struct DevCtx {
     uint64_t* masks = nullptr;
     double2* terms = nullptr;
     size_t masks_cap = 0;
+    // lane grid per (n, s); -1 = heuristic default
+    int layout[gbs::kMaxPairs + 1][gbs::kMaxPairs + 1];
+    bool tuned[gbs::kMaxPairs + 1];
+    char name[64] = {0};
+    DevCtx() {
+        for (auto& row : layout)
+            for (int& v : row) v = -1;
+        for (bool& t : tuned) t = false;
+    }
 };
+
+// Consults the autotune cache / runs the tuner once per n (uses the workspace,
+// so it is called before the caller's matrix is prepared).
+gbs_status maybe_tune(DevCtx* c, int n);
+
+int layout_for(const DevCtx* c, int n, int s) {
+    const int v = c->layout[n][s];
+    return v >= 0 ? v : gbs::charpoly_default_layout(2 * s);
+}
 
 std::mutex g_mutex;
 std::map<int, DevCtx*> g_ctx;
@@ -146,6 +165,12 @@ gbs_status ctx_create(int device, DevCtx** out) {
     HIP_TRY(hipMalloc((void**)&c->Ain, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
     HIP_TRY(hipMalloc((void**)&c->res, sizeof(double2) * 2));
     HIP_TRY(hipEventRecord(c->done, c->stream));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        snprintf(c->name, sizeof c->name, "%s", prop.gcnArchName);
+        for (char* q = c->name; *q; ++q)
+            if (*q == ' ' || *q == ':') *q = '_';
+    }
     *out = c;
     return GBS_OK;
 }
@@ -276,8 +301,9 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
         for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
             const uint64_t len = std::min(kChunk, cnt - st0);
             gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, c->E};
+            const int lay = layout_for(c, n, s);
             HIP_TRY(timed_launch(kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
-                                 [&] { return gbs::launch_charpoly(p1, st); }));
+                                 [&] { return gbs::launch_charpoly(p1, lay, st); }));
             gbs::LaunchPhase2 p2{c->E, len, D, sign, kPerThread, c->partials + 5 * poff, nullptr};
             HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, st, [&] { return gbs::launch_series(n, p2, st); }));
             poff += (len + per_block - 1) / per_block;
@@ -297,6 +323,8 @@ gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* dia
     gbs_status st = current_ctx(&c);
     if (st != GBS_OK) return st;
     const int Np = N + (N & 1);
+    st = maybe_tune(c, Np / 2);
+    if (st != GBS_OK) return st;
     HIP_TRY(hipStreamWaitEvent(c->stream, c->done, 0));
     if (N > 0) HIP_TRY(hipMemcpyAsync(c->Ain, A, sizeof(gbs_z) * (size_t)N * N, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipEventRecord(c->t0, c->stream));
@@ -558,6 +586,8 @@ gbs_status gbs_lhaf_terms(const gbs_z* A, int32_t N, int64_t lda, const uint64_t
     std::vector<gbs_z> Ah((size_t)N * N);
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j) Ah[(size_t)i * N + j] = A[(int64_t)i * lda + j];
+    st = maybe_tune(c, n);
+    if (st != GBS_OK) return st;
     HIP_TRY(hipStreamWaitEvent(c->stream, c->done, 0));
     HIP_TRY(hipMemcpyAsync(c->Ain, Ah.data(), sizeof(gbs_z) * Ah.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(gbs::launch_prep(c->Ain, N, N, Np, c->A0, c->dvec, c->stream));
@@ -589,7 +619,7 @@ gbs_status gbs_lhaf_terms(const gbs_z* A, int32_t N, int64_t lda, const uint64_t
             if (st != GBS_OK) return st;
             HIP_TRY(hipMemcpyAsync(c->masks, grp.data() + off, sizeof(uint64_t) * len, hipMemcpyHostToDevice, c->stream));
             gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, c->E};
-            HIP_TRY(gbs::launch_charpoly(p1, c->stream));
+            HIP_TRY(gbs::launch_charpoly(p1, layout_for(c, n, s), c->stream));
             gbs::LaunchPhase2 p2{c->E, len, D, ((n - s) & 1) ? -1.0 : 1.0, kPerThread, c->partials, c->terms};
             HIP_TRY(gbs::launch_series(n, p2, c->stream));
             std::vector<double2> th(len);
@@ -615,6 +645,8 @@ gbs_status gbs_lhaf_device(const gbs_z* A_dev, int32_t N, gbs_precision prec, gb
     if (st != GBS_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int Np = N + (N & 1);
+    st = maybe_tune(c, Np / 2);
+    if (st != GBS_OK) return st;
     HIP_TRY(hipStreamWaitEvent(s, c->done, 0));
     if (Np > 0)
         HIP_TRY(gbs::launch_prep(reinterpret_cast<const double2*>(A_dev), N, N, Np, c->A0, c->dvec, s));
@@ -670,6 +702,132 @@ double gbs_yardstick_flops(int32_t N) {
     double f = 0.0;
     for (int s = 1; s <= n; ++s) f += (double)binom_host(n, s) * subset_flops(n, s);
     return f;
+}
+
+gbs_status gbs_set_layout(int32_t n, int32_t s, int32_t layout) {
+    if (n < 0 || n > gbs::kMaxPairs || s < 0 || s > gbs::kMaxPairs) return fail(GBS_E_ARG, "bad (n, s)");
+    if (layout < -1 || layout >= gbs::kNumLayouts) return fail(GBS_E_ARG, "bad layout %d", layout);
+    if (s > 0 && layout >= 0 && !gbs::charpoly_layout_ok(2 * s, layout))
+        return fail(GBS_E_ARG, "layout %d cannot hold m = %d", layout, 2 * s);
+    std::lock_guard<std::mutex> lock(g_mutex);
+    DevCtx* c = nullptr;
+    gbs_status st = current_ctx(&c);
+    if (st != GBS_OK) return st;
+    for (int nn = (n ? n : 1); nn <= (n ? n : gbs::kMaxPairs); ++nn)
+        for (int ss = (s ? s : 1); ss <= (s ? s : nn); ++ss)
+            if (layout < 0 || gbs::charpoly_layout_ok(2 * ss, layout)) c->layout[nn][ss] = layout;
+    return GBS_OK;
+}
+
+namespace {
+
+// Reads "<arch> <n> <s> <layout>" lines of the autotune cache for this device.
+bool cache_load(DevCtx* c, int n) {
+    const char* path = std::getenv("GBS_AUTOTUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char arch[64];
+    int nn, ss, lay;
+    bool any = false;
+    while (std::fscanf(f, "%63s %d %d %d", arch, &nn, &ss, &lay) == 4) {
+        if (nn == n && std::strcmp(arch, c->name) == 0 && ss >= 1 && ss <= n && lay >= 0 &&
+            lay < gbs::kNumLayouts && gbs::charpoly_layout_ok(2 * ss, lay)) {
+            c->layout[n][ss] = lay;
+            any = true;
+        }
+    }
+    std::fclose(f);
+    return any;
+}
+
+void cache_store(const DevCtx* c, int n) {
+    const char* path = std::getenv("GBS_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    for (int s = 1; s <= n; ++s) std::fprintf(f, "%s %d %d %d\n", c->name, n, s, c->layout[n][s]);
+    std::fclose(f);
+}
+
+// Times each valid lane grid per subset size on a synthetic matrix.
+gbs_status autotune_impl(DevCtx* c, int n, gbs_tune_report* rep) {
+    const int Np = 2 * n, D = n + 1;
+    std::vector<gbs_z> Ah((size_t)Np * Np);
+    uint64_t x = 0x9E3779B97F4A7C15ull;
+    auto rnd = [&]() {
+        x ^= x << 13;
+        x ^= x >> 7;
+        x ^= x << 17;
+        return (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    };
+    for (int i = 0; i < Np; ++i)
+        for (int j = 0; j <= i; ++j) {
+            const gbs_z z{0.3 * rnd(), 0.3 * rnd()};
+            Ah[(size_t)i * Np + j] = z;
+            Ah[(size_t)j * Np + i] = z;
+        }
+    HIP_TRY(hipStreamWaitEvent(c->stream, c->done, 0));
+    HIP_TRY(hipMemcpyAsync(c->Ain, Ah.data(), sizeof(gbs_z) * Ah.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(gbs::launch_prep(c->Ain, Np, Np, Np, c->A0, c->dvec, c->stream));
+    const uint64_t sample_cap = 1ull << 16;
+    uint64_t max_len = 0;
+    for (int s = 1; s <= n; ++s) max_len = std::max(max_len, std::min(sample_cap, binom_host(n, s)));
+    gbs_status st = ensure_buffer((void**)&c->E, &c->E_cap, (size_t)max_len * 2 * (D + 1), sizeof(double2));
+    if (st != GBS_OK) return st;
+    if (rep) {
+        std::memset(rep, 0, sizeof *rep);
+        rep->n = n;
+    }
+    for (int s = 1; s <= n; ++s) {
+        const uint64_t len = std::min(sample_cap, binom_host(n, s));
+        double best = 1e300;
+        int best_lay = gbs::charpoly_default_layout(2 * s);
+        for (int lay = 0; lay < gbs::kNumLayouts; ++lay) {
+            if (!gbs::charpoly_layout_ok(2 * s, lay)) continue;
+            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, nullptr, c->binom, D, c->E};
+            HIP_TRY(gbs::launch_charpoly(p1, lay, c->stream));  // warm-up
+            HIP_TRY(hipEventRecord(c->t0, c->stream));
+            const int reps = 3;
+            for (int r = 0; r < reps; ++r) HIP_TRY(gbs::launch_charpoly(p1, lay, c->stream));
+            HIP_TRY(hipEventRecord(c->t1, c->stream));
+            HIP_TRY(hipEventSynchronize(c->t1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, c->t0, c->t1));
+            const double ns = 1e6 * ms / (reps * (double)len);
+            if (rep) rep->ns_per_subset[s][lay] = ns;
+            if (ns < best) {
+                best = ns;
+                best_lay = lay;
+            }
+        }
+        c->layout[n][s] = best_lay;
+        if (rep) rep->layout[s] = best_lay;
+    }
+    HIP_TRY(hipEventRecord(c->done, c->stream));
+    c->tuned[n] = true;
+    cache_store(c, n);
+    return GBS_OK;
+}
+
+gbs_status maybe_tune(DevCtx* c, int n) {
+    if (n < 1 || n > gbs::kMaxPairs || c->tuned[n]) return GBS_OK;
+    c->tuned[n] = true;
+    if (cache_load(c, n)) return GBS_OK;
+    const char* at = std::getenv("GBS_AUTOTUNE");
+    if (at && (std::strcmp(at, "1") == 0 || std::strcmp(at, "force") == 0)) return autotune_impl(c, n, nullptr);
+    return GBS_OK;
+}
+
+}  // namespace
+
+gbs_status gbs_autotune(int32_t n, gbs_tune_report* report) {
+    if (n < 1 || n > gbs::kMaxPairs) return fail(GBS_E_ARG, "n = %d out of range", n);
+    std::lock_guard<std::mutex> lock(g_mutex);
+    DevCtx* c = nullptr;
+    gbs_status st = current_ctx(&c);
+    if (st != GBS_OK) return st;
+    return autotune_impl(c, n, report);
 }
 
 gbs_status gbs_selftest(int32_t* failures) {

@@ -1,0 +1,547 @@
+#pragma once
+// Device code shared by the loop-hafnian kernels (gfx950 / CDNA4): complex
+// arithmetic, wavefront cross-lane sums and the per-subset kernel template.
+//
+// Method (Quesada et al., arXiv:2010.15595, Sec. IV; algorithm of its
+// Ref. [bjorklund2018faster]): with N = 2n, pairs (i, i+n), A0 = A with zero
+// diagonal and d = diag(A), for every pair subset S of size s (m = 2s)
+//     C = X_S A0_S,   c_k = tr(C^k) / (2k) + d_S^T C^(k-1) X_S d_S / 2,
+//     t_S = (-1)^(n-s) [eta^n] exp(sum_k c_k eta^k),       lhaf = sum_S t_S.
+//
+// GPU formulation (differs from the paper's CPU code, same value):
+//  * The loop terms come from a bordered determinant instead of mat-vecs:
+//    with C' = [[0, d_S^T], [X_S d_S, C]],
+//        det(I - eta C') = det(I - eta C) (1 - eta^2 d^T (I - eta C)^-1 X d),
+//    so sum_k q_k eta^k = (R(eta) - R'(eta)) / (eta R(eta)) with
+//    R = det(I - eta C), R' = det(I - eta C').
+//  * C' is reduced to upper Hessenberg H' by Householder reflectors in
+//    registers: the border column is the first reflector (it maps X d to a
+//    multiple of e_1), then the Householder steps of C; the border row only
+//    receives right applications.  H'[1:,1:] is similar to C, H' to C'.
+//  * La Budde's recurrence (Rehman & Ipsen 2011) is run over the trailing
+//    principal blocks of H' (expansion along the first row of each trailing
+//    block), so one pass yields both det(xI - C) and det(xI - C').  Only the
+//    n+2 leading coefficients are carried (lane d holds the coefficient of
+//    x^(size-d)).
+//  * A second kernel (one lane per subset) forms the power traces by Newton's
+//    identities, the loop terms by power-series division, and the
+//    exp-series coefficient; partial sums are compensated (TwoSum) and reduced
+//    in a fixed order, so results are bitwise reproducible.
+//
+// Register layout of the m x m Hessenberg work: a wavefront holds W = 64/(P Q)
+// subsets of one size class; lane l = g (P Q) + pc P + pr serves subset g and
+// owns rows r = pr + P i (i < MR) and columns c = pc + Q k (k < MC).  Column
+// sums reduce over the P consecutive lanes (DPP quad_perm / row_half_mirror),
+// row sums over the Q lanes of stride P (DPP row_ror plus the gfx950
+// permlane16/32 swaps).  Lane grids: 8x8 (one subset per wave), 8x4 (two),
+// 4x4 (four); the choice per subset size is made by the host (autotuned).
+
+#include "lhaf_kernels.h"
+
+namespace gbs {
+
+// ---------------------------------------------------------------- complex
+
+__device__ __forceinline__ double2 cz() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// c + a * b
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
+    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+// c - a * b
+__device__ __forceinline__ double2 cfms(double2 a, double2 b, double2 c) {
+    return make_double2(fma(-a.x, b.x, fma(a.y, b.y, c.x)), fma(-a.x, b.y, fma(-a.y, b.x, c.y)));
+}
+// c + conj(a) * b
+__device__ __forceinline__ double2 cfma_ca(double2 a, double2 b, double2 c) {
+    return make_double2(fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y)));
+}
+// c - a * conj(b)
+__device__ __forceinline__ double2 cfms_cb(double2 a, double2 b, double2 c) {
+    return make_double2(fma(-a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
+
+// ---------------------------------------------------------------- cross-lane
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+    int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 8 lanes of an aligned octet; every lane of the octet gets the
+// same bits (each butterfly level adds the same two operands, commuted).
+__device__ __forceinline__ double sum_octet(double x) {
+    x += dpp_mov<0x141>(x);  // row_half_mirror: lane i <- lane 7 - i
+    x += dpp_mov<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]
+    return x;
+}
+
+__device__ __forceinline__ double swap_sum16(double x) {
+    unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+    auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+
+__device__ __forceinline__ double swap_sum32(double x) {
+    unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+    auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+
+// Sum over the 8 lanes {l mod 8 + 8 q : q = 0..7}.
+__device__ __forceinline__ double sum_stride8(double x) {
+    x += dpp_mov<0x128>(x);  // row_ror:8 -> partner lane l ^ 8
+    x = swap_sum16(x);       // partner l ^ 16
+    x = swap_sum32(x);       // partner l ^ 32
+    return x;
+}
+
+__device__ __forceinline__ double2 csum_octet(double2 a) { return make_double2(sum_octet(a.x), sum_octet(a.y)); }
+__device__ __forceinline__ double2 csum_stride8(double2 a) { return make_double2(sum_stride8(a.x), sum_stride8(a.y)); }
+
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double2 readlane_c(double2 a, int lane) {
+    return make_double2(readlane_d(a.x, lane), readlane_d(a.y, lane));
+}
+
+// Order LDS traffic between the lanes of one wavefront (no block barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// ---------------------------------------------------------------- subsets
+
+// s-subset of {0..n-1} with colexicographic rank `rank`:
+// rank = sum_i C(c_i, i) over its elements c_1 < ... < c_s.
+__device__ __forceinline__ uint64_t unrank_colex(uint64_t rank, int n, int s, const uint64_t* __restrict__ binom) {
+    uint64_t mask = 0;
+    int c = n - 1;
+    for (int i = s; i >= 1; --i) {
+        while (binom[c * kBinomStride + i] > rank) --c;
+        mask |= 1ull << c;
+        rank -= binom[c * kBinomStride + i];
+        --c;
+    }
+    return mask;
+}
+
+// ---------------------------------------------------------------- phase 1
+
+// Lane grids.  A wavefront holds W = 64 / (P Q) subsets of one size class.
+// Lane l = g (P Q) + pc P + pr serves subset group g and owns rows
+// r = pr + P i (i < MR) and columns c = pc + Q k (k < MC) of its subset's matrix.
+
+// Sum over the P consecutive lanes pr = 0..P-1 (P = 4 or 8).
+template <int P>
+__device__ __forceinline__ double sum_cols(double x) {
+    if constexpr (P == 8) x += dpp_mov<0x141>(x);  // row_half_mirror
+    x += dpp_mov<0xB1>(x);                          // quad_perm [1,0,3,2]
+    x += dpp_mov<0x4E>(x);                          // quad_perm [2,3,0,1]
+    return x;
+}
+
+// Sum over the Q lanes pc = 0..Q-1 (stride P) of one group.  Each level adds
+// two values that the partner lane adds in the other order, so all Q lanes end
+// with the same bits.
+template <int P, int Q>
+__device__ __forceinline__ double sum_rows(double x) {
+    if constexpr (P == 8 && Q == 8) {
+        x += dpp_mov<0x128>(x);  // row_ror:8 (lane ^ 8)
+        x = swap_sum16(x);       // lane ^ 16
+        x = swap_sum32(x);       // lane ^ 32
+    } else if constexpr (P == 8 && Q == 4) {
+        x += dpp_mov<0x128>(x);
+        x = swap_sum16(x);
+    } else if constexpr (P == 4 && Q == 4) {
+        x += dpp_mov<0x128>(x);  // pair sums, equal in lanes i and i ^ 8
+        x += dpp_mov<0x124>(x);  // row_ror:4 adds the other pair
+    } else {
+        static_assert(P == 4 && Q == 8, "unsupported lane grid");
+        x += dpp_mov<0x128>(x);
+        x += dpp_mov<0x124>(x);
+        x = swap_sum16(x);
+    }
+    return x;
+}
+
+template <int P>
+__device__ __forceinline__ double2 csum_cols(double2 a) { return make_double2(sum_cols<P>(a.x), sum_cols<P>(a.y)); }
+template <int P, int Q>
+__device__ __forceinline__ double2 csum_rows(double2 a) { return make_double2(sum_rows<P, Q>(a.x), sum_rows<P, Q>(a.y)); }
+
+// 1/sqrt(x), x > 0: hardware estimate and two Newton steps (full FP64 accuracy).
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// Householder reflector P = I - v v^H (|v|^2 = 2) with P x = -phase |x| e_1:
+// from |x|^2 and the head x0, returns the scale of the tail (v_r = x_r scale),
+// the head of v and the new subdiagonal entry.  |x| = 0 gives v = 0.
+__device__ __forceinline__ void householder(double norm2, double2 x0, double& scale, double2& vhead,
+                                            double2& newsub) {
+    if (norm2 > 0.0) {
+        const double xnorm = norm2 * rsq_nr(norm2);
+        const double ax2 = cabs2(x0);
+        double2 phase = make_double2(1.0, 0.0);
+        double ax0 = 0.0;
+        if (ax2 > 0.0) {
+            const double ra = rsq_nr(ax2);
+            ax0 = ax2 * ra;
+            phase = cscale(x0, ra);
+        }
+        scale = rsq_nr(fma(ax0, xnorm, norm2));
+        vhead = cscale(phase, (ax0 + xnorm) * scale);
+        newsub = cscale(phase, -xnorm);
+    } else {
+        scale = 0.0;
+        vhead = cz();
+        newsub = cz();
+    }
+}
+
+struct Lds {
+    double2* vbuf;   // [W][64]: source column of the current reflector
+    double2* misc;   // [W][2]: squared norm, alpha (border subdiagonal)
+    int* idx;        // [W][64]: vertex indices of the subset
+    double2* rowbuf; // [NT][64]: current row of H' (La Budde)
+    double2* betab;  // [NT][64]: beta_k of the current row
+    double2* ring;   // [NT][RS * RS]: last RS trailing characteristic polynomials
+};
+
+__host__ __device__ constexpr int lds_doubles2(int W, int NT, int D) {
+    return W * (64 + 2 + 16) + NT * (128 + (D + 1) * (D + 1));
+}
+
+template <int P, int Q, int MR, int MC, int KJ>
+__device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC], int m, int pr, int pc,
+                                           double2* __restrict__ vb, double2* __restrict__ nb) {
+    constexpr int IL = (Q * KJ) / P;  // local rows below IL lie above every column of this phase
+    for (int jj = 0; jj < Q; ++jj) {
+        const int j = Q * KJ + jj;
+        if (j > m - 3) return;
+        wave_sync();
+        if (pc == jj) {
+            double part = 0.0;
+#pragma unroll
+            for (int i = IL; i < MR; ++i) {
+                const int r = pr + P * i;
+                const double2 x = (r >= j + 1) ? a[i][KJ] : cz();
+                vb[r] = x;
+                part += cabs2(x);
+            }
+            part = sum_cols<P>(part);
+            if (pr == 0) nb[0] = make_double2(part, 0.0);
+        }
+        wave_sync();
+        const double norm2 = nb[0].x;
+        const double2 x0 = vb[j + 1];
+        double scale;
+        double2 vhead, newsub;
+        householder(norm2, x0, scale, vhead, newsub);
+        double2 vr[MR], vc[MC];
+#pragma unroll
+        for (int i = IL; i < MR; ++i) {
+            const int r = pr + P * i;
+            vr[i] = (r == j + 1) ? vhead : cscale(vb[r], scale);
+        }
+#pragma unroll
+        for (int k = KJ; k < MC; ++k) {
+            const int c = pc + Q * k;
+            vc[k] = (c == j + 1) ? vhead : cscale(vb[c], scale);
+        }
+        // left: H <- (I - v v^H) H
+#pragma unroll
+        for (int k = KJ; k < MC; ++k) {
+            double2 w = cz();
+#pragma unroll
+            for (int i = IL; i < MR; ++i) w = cfma_ca(vr[i], a[i][k], w);
+            w = csum_cols<P>(w);
+#pragma unroll
+            for (int i = IL; i < MR; ++i) a[i][k] = cfms(vr[i], w, a[i][k]);
+        }
+        if (pc == jj) {
+#pragma unroll
+            for (int i = IL; i < MR; ++i) {
+                const int r = pr + P * i;
+                if (r == j + 1) a[i][KJ] = newsub;
+                else if (r > j + 1) a[i][KJ] = cz();
+            }
+        }
+        // right: H <- H (I - v v^H); border row y^T <- y^T (I - v v^H)
+#pragma unroll
+        for (int i = 0; i < MR; ++i) {
+            double2 u = cz();
+#pragma unroll
+            for (int k = KJ; k < MC; ++k) u = cfma(a[i][k], vc[k], u);
+            u = csum_rows<P, Q>(u);
+#pragma unroll
+            for (int k = KJ; k < MC; ++k) a[i][k] = cfms_cb(u, vc[k], a[i][k]);
+        }
+        double2 sy = cz();
+#pragma unroll
+        for (int k = KJ; k < MC; ++k) sy = cfma(y[k], vc[k], sy);
+        sy = csum_rows<P, Q>(sy);
+#pragma unroll
+        for (int k = KJ; k < MC; ++k) y[k] = cfms_cb(sy, vc[k], y[k]);
+    }
+}
+
+template <int P, int Q, int MR, int MC, int KJ>
+__device__ __forceinline__ void hess_all(double2 (&a)[MR][MC], double2 (&y)[MC], int m, int pr, int pc,
+                                         double2* __restrict__ vb, double2* __restrict__ nb) {
+    if constexpr (KJ < MC) {
+        if (Q * KJ > m - 3) return;
+        hess_phase<P, Q, MR, MC, KJ>(a, y, m, pr, pc, vb, nb);
+        hess_all<P, Q, MR, MC, KJ + 1>(a, y, m, pr, pc, vb, nb);
+    }
+}
+
+// One La Budde step (team-local): row r = rho + 1 of H' is in rowbuf at
+// index rho + k for H'[r][r + k]; sub_in = H'[r + 1][r].  Team lane d updates
+// coefficient d of the trailing polynomial of rows r.. (ring slot r % RS).
+__device__ __forceinline__ void labudde_step(int rho, int m, int D, int d, double2 hrr, double2 sub_in, double2& pik,
+                                             const double2* __restrict__ rowbuf, double2* __restrict__ betab,
+                                             double2* __restrict__ ring) {
+    const int RS = D + 1;
+    const int r = rho + 1;
+    // pi_{r,k} = H'[r+1][r] pi_{r+1,k-1} (lane shift by one), pi_{r,0} = 1
+    const double2 sh = make_double2(dpp_mov<0x138>(pik.x), dpp_mov<0x138>(pik.y));  // wave_shr:1
+    pik = (d == 0) ? make_double2(1.0, 0.0) : cmul(sub_in, sh);
+    const int K = min(D - 1, m - rho - 1);
+    if (d >= 1 && d <= K) betab[d] = cmul(rowbuf[rho + d], pik);
+    wave_sync();
+    if (d <= D) {
+        const double2* prev = ring + ((r + 1) % RS) * RS;
+        double2 e = prev[d];
+        if (d >= 1) e = cfms(hrr, prev[d - 1], e);
+        const int kmax = min(K, d - 1);
+        // element of poly r+k+1 at coefficient d-k-1: ring[slot(k) * RS + d - k - 1]
+        int slot = (r + 2) % RS;
+        const double2* base = ring + d - 1;
+        for (int k = 1; k <= kmax; ++k) {
+            e = cfms(betab[k], base[slot * RS - k], e);
+            slot = (slot + 1 == RS) ? 0 : slot + 1;
+        }
+        ring[(r % RS) * RS + d] = e;
+    }
+    wave_sync();
+}
+
+template <int P, int Q, int MR, int MC, int I>
+__device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, int D, int d, int pr, int pc,
+                                             bool row_owner_group, double2* __restrict__ rowbuf_own,
+                                             const double2* __restrict__ rowbuf, double2* __restrict__ betab,
+                                             double2* __restrict__ ring, double2& pik, double2& sub) {
+    if constexpr (I >= 0) {
+        for (int p = P - 1; p >= 0; --p) {
+            const int rho = p + P * I;
+            if (rho >= m) continue;
+            if (row_owner_group && pr == p) {
+#pragma unroll
+                for (int k = 0; k < MC; ++k) rowbuf_own[pc + Q * k] = a[I][k];
+            }
+            wave_sync();
+            const double2 hrr = rowbuf[rho];
+            const double2 sub_next = (rho >= 1) ? rowbuf[rho - 1] : cz();
+            labudde_step(rho, m, D, d, hrr, sub, pik, rowbuf, betab, ring);
+            sub = sub_next;
+        }
+        labudde_rows<P, Q, MR, MC, I - 1>(a, m, D, d, pr, pc, row_owner_group, rowbuf_own, rowbuf, betab, ring, pik,
+                                          sub);
+    }
+}
+
+template <int P, int Q, int MR, int MC>
+__global__ void __launch_bounds__(64) charpoly_kernel(const double2* __restrict__ A0, const double2* __restrict__ dvec,
+                                                      int Np, int s, uint64_t rank0, uint64_t count,
+                                                      const uint64_t* __restrict__ masks,
+                                                      const uint64_t* __restrict__ binom, int D, int T,
+                                                      double2* __restrict__ Eout) {
+    constexpr int G = P * Q;
+    constexpr int W = 64 / G;
+    extern __shared__ double2 lds[];
+    const int lane = threadIdx.x;
+    const int g = lane / G;
+    const int pr = lane % P;
+    const int pc = (lane / P) % Q;
+    const int n = Np >> 1;
+    const int m = 2 * s;
+    const int NT = 64 / T;
+    const int RS = D + 1;
+    Lds L;
+    L.vbuf = lds;
+    L.misc = lds + W * 64;
+    L.idx = reinterpret_cast<int*>(lds + W * 66);
+    L.rowbuf = lds + W * 82;
+    L.betab = L.rowbuf + NT * 64;
+    L.ring = L.betab + NT * 64;
+    double2* vb = L.vbuf + g * 64;
+    double2* nb = L.misc + g * 2;
+    int* idx = L.idx + g * 64;
+
+    // subsets of this wave (one per group); the mask list or colex unranking
+    // is evaluated on the scalar unit for every group, then selected per lane
+    const uint64_t first = (uint64_t)blockIdx.x * W;
+    uint64_t mask = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        const uint64_t gi = (first + q < count) ? first + q : count - 1;
+        const uint64_t mq = masks ? masks[gi] : unrank_colex(rank0 + gi, n, s, binom);
+        if (g == q) mask = mq;
+    }
+    for (int e = lane; e < W * 64; e += 64) L.vbuf[e] = cz();
+    {
+        const int b = lane % G;  // each group lane b < n scans vertex b
+        if (b < n && ((mask >> b) & 1ull)) {
+            const int pos = __popcll(mask & ((1ull << b) - 1ull));
+            idx[pos] = b;
+            idx[pos + s] = b + n;
+        }
+        if (G < 32) {  // groups narrower than n: lanes scan vertices b + G, b + 2G, ...
+            for (int bb = b + G; bb < n; bb += G) {
+                if ((mask >> bb) & 1ull) {
+                    const int pos = __popcll(mask & ((1ull << bb) - 1ull));
+                    idx[pos] = bb;
+                    idx[pos + s] = bb + n;
+                }
+            }
+        }
+    }
+    wave_sync();
+
+    // gather C = X_S A0_S, border row y = d_S and border column z = X_S d_S
+    double2 a[MR][MC];
+    double2 y[MC];
+    double2 zr[MR], zc[MC];
+#pragma unroll
+    for (int i = 0; i < MR; ++i) {
+        const int r = pr + P * i;
+        const bool rok = r < m;
+        const int xr = (r < s) ? r + s : r - s;
+        const int vr = rok ? idx[xr] : 0;
+        zr[i] = rok ? dvec[vr] : cz();
+#pragma unroll
+        for (int k = 0; k < MC; ++k) {
+            const int c = pc + Q * k;
+            const bool ok = rok && c < m;
+            const int off = ok ? vr * Np + idx[c] : 0;
+            const double2 v = A0[off];
+            a[i][k] = ok ? v : cz();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < MC; ++k) {
+        const int c = pc + Q * k;
+        const bool ok = c < m;
+        const int xc = (c < s) ? c + s : c - s;
+        const double2 dy = dvec[ok ? idx[c] : 0];
+        const double2 dz = dvec[ok ? idx[xc] : 0];
+        y[k] = ok ? dy : cz();
+        zc[k] = ok ? dz : cz();
+    }
+
+    // border reflector: maps z to alpha e_1, applied to C from both sides
+    double2 alpha;
+    {
+        double part = 0.0;
+#pragma unroll
+        for (int i = 0; i < MR; ++i) part += cabs2(zr[i]);
+        const double norm2 = sum_cols<P>(part);
+        const double2 x0 = dvec[idx[s]];  // z_0 = loop weight of the partner of vertex 0
+        double scale;
+        double2 vhead;
+        householder(norm2, x0, scale, vhead, alpha);
+        double2 vr[MR], vc[MC];
+#pragma unroll
+        for (int i = 0; i < MR; ++i) vr[i] = (pr + P * i == 0) ? vhead : cscale(zr[i], scale);
+#pragma unroll
+        for (int k = 0; k < MC; ++k) vc[k] = (pc + Q * k == 0) ? vhead : cscale(zc[k], scale);
+#pragma unroll
+        for (int k = 0; k < MC; ++k) {
+            double2 w = cz();
+#pragma unroll
+            for (int i = 0; i < MR; ++i) w = cfma_ca(vr[i], a[i][k], w);
+            w = csum_cols<P>(w);
+#pragma unroll
+            for (int i = 0; i < MR; ++i) a[i][k] = cfms(vr[i], w, a[i][k]);
+        }
+#pragma unroll
+        for (int i = 0; i < MR; ++i) {
+            double2 u = cz();
+#pragma unroll
+            for (int k = 0; k < MC; ++k) u = cfma(a[i][k], vc[k], u);
+            u = csum_rows<P, Q>(u);
+#pragma unroll
+            for (int k = 0; k < MC; ++k) a[i][k] = cfms_cb(u, vc[k], a[i][k]);
+        }
+        double2 sy = cz();
+#pragma unroll
+        for (int k = 0; k < MC; ++k) sy = cfma(y[k], vc[k], sy);
+        sy = csum_rows<P, Q>(sy);
+#pragma unroll
+        for (int k = 0; k < MC; ++k) y[k] = cfms_cb(sy, vc[k], y[k]);
+    }
+    if (lane % G == 0) nb[1] = alpha;
+
+    // Householder reduction of the C block
+    hess_all<P, Q, MR, MC, 0>(a, y, m, pr, pc, vb, nb);
+
+    // La Budde over the trailing blocks of H' (size m + 1).  Team t of T lanes
+    // handles group t + NT * pass; lane d of the team holds coefficient d.
+    const int team = lane / T;
+    const int d = lane % T;
+    const int Mp = m + 1;
+    for (int pass = 0; pass < W / NT; ++pass) {
+        const int gt = pass * NT + team;          // group served by my team
+        const bool own = (g / NT) == pass;        // my group's rows are read this pass
+        double2* rowbuf_own = L.rowbuf + (g % NT) * 64;
+        double2* rowbuf = L.rowbuf + team * 64;
+        double2* betab = L.betab + team * 64;
+        double2* ring = L.ring + team * RS * RS;
+        if (d < RS) ring[(Mp % RS) * RS + d] = (d == 0) ? make_double2(1.0, 0.0) : cz();
+        double2 pik = (d == 0) ? make_double2(1.0, 0.0) : cz();
+        double2 sub = cz();
+        wave_sync();
+        labudde_rows<P, Q, MR, MC, MR - 1>(a, m, D, d, pr, pc, own, rowbuf_own, rowbuf, betab, ring, pik, sub);
+        // border row: H'[0][k] = y''_{k-1}, H'[0][0] = 0, H'[1][0] = alpha
+        if (own && pr == 0) {
+#pragma unroll
+            for (int k = 0; k < MC; ++k) rowbuf_own[pc + Q * k] = y[k];
+        }
+        wave_sync();
+        const double2 alpha_t = L.misc[gt * 2 + 1];
+        labudde_step(-1, m, D, d, cz(), alpha_t, pik, rowbuf, betab, ring);
+        const uint64_t gi = first + gt;
+        if (d <= D && gi < count) {
+            double2* out = Eout + gi * (uint64_t)(2 * RS);
+            out[d] = ring[(1 % RS) * RS + d];
+            out[RS + d] = ring[d];
+        }
+        wave_sync();
+    }
+}
+
+}  // namespace gbs

@@ -35,8 +35,11 @@ struct LaunchPhase2 {
     double2* terms;     // optional per-subset terms
 };
 
-hipError_t launch_charpoly(const LaunchPhase1& p, hipStream_t st);
-size_t charpoly_lds_bytes(int D);
+// Lane grids of the per-subset kernel (rows x columns of lanes per subset).
+enum { kLayout44 = 0, kLayout84 = 1, kLayout88 = 2, kNumLayouts = 3 };
+bool charpoly_layout_ok(int m, int layout);
+int charpoly_default_layout(int m);
+hipError_t launch_charpoly(const LaunchPhase1& p, int layout, hipStream_t st);
 hipError_t launch_series(int n, const LaunchPhase2& p, hipStream_t st);
 hipError_t launch_final_reduce(const double* partials, int64_t np, double2* out, double* abs_out, hipStream_t st);
 hipError_t launch_prep(const double2* A, int N, int64_t lda, int Np, double2* A0, double2* d, hipStream_t st);

@@ -255,3 +255,43 @@ def test_allones_accuracy_report(gbs):
         print(f"[Fig.2 n={n}] fp64 gpu rel err {rel:.2e} (paper, long double: {paper[n]:.2e}); "
               f"kappa {d['kappa']:.2e}", flush=True)
         assert abs(val - T) <= NORMWISE * d["abs_sum"]
+
+
+@pytest.mark.parametrize("layout,N", [(0, 24), (1, 24), (2, 24), (1, 40), (2, 40)])
+def test_every_lane_grid_matches_oracle(gbs, layout, N):
+    """Each lane grid of the per-subset kernel (4x4, 8x4, 8x8), forced for all
+    subset sizes, against the oracle: full sum at N = 24, sampled terms at 40."""
+    st = workloads.config3(N, seed=5)
+    A = oracle.expand(st["B"], st["gamma"], st["pattern"])
+    gbs.set_layout(0, 0, layout)
+    try:
+        if N <= 24:
+            val, d = gbs.lhaf(A, with_diag=True)
+            ref = oracle.to_complex(oracle.lhaf_pt(A, prec="ld"))
+            assert report(f"layout {layout} N={N}", val, ref, d["abs_sum"])
+        else:
+            masks = _sample_masks(N // 2, 4, seed=layout)
+            got = gbs.lhaf_terms(A, masks)
+            ref = oracle.terms(A, masks, prec="ld")
+            worst = np.max(np.abs(got - ref) / np.abs(ref))
+            print(f"[layout {layout} terms N={N}] worst rel {worst:.2e}", flush=True)
+            assert worst <= 1e-9
+    finally:
+        gbs.set_layout(0, 0, -1)
+
+
+def test_layout_rejects_too_small_grid(gbs):
+    with pytest.raises(gbs.GbsError):
+        gbs.set_layout(20, 15, 0)  # 4x4 holds m <= 24, s = 15 needs m = 30
+
+
+def test_autotune_then_parity(gbs):
+    rep = gbs.autotune(14)
+    assert set(rep) == set(range(1, 15))
+    for s, (lay, times) in rep.items():
+        assert lay in times and times[lay] == min(times.values())
+    print("[autotune n=14] " + ", ".join(f"s={s}:{lay}" for s, (lay, _) in rep.items()), flush=True)
+    A = workloads.random_normal_symmetric(28, seed=3, scale=0.4)
+    val, d = gbs.lhaf(A, with_diag=True)
+    ref = oracle.to_complex(oracle.lhaf_pt(A, prec="ld"))
+    assert report("after autotune N=28", val, ref, d["abs_sum"])
