@@ -836,7 +836,7 @@ gbs_status gbs_selftest(int32_t* failures) {
     DevCtx* c = nullptr;
     gbs_status st = current_ctx(&c);
     if (st != GBS_OK) return st;
-    double hin[64], hout[256];
+    double hin[64], hout[1152];
     for (int l = 0; l < 64; ++l) hin[l] = std::ldexp(1.0, l % 20) + 0.25 * l;
     double *din = nullptr, *dout = nullptr;
     HIP_TRY(hipMalloc((void**)&din, sizeof hin));
@@ -856,6 +856,24 @@ gbs_status gbs_selftest(int32_t* failures) {
         if (std::fabs(hout[64 + l] - ss) > 1e-12 * std::fabs(ss)) ++bad;
         if (hout[128 + l] != hin[37]) ++bad;
         if (l >= 1 && hout[192 + l] != hin[l - 1]) ++bad;
+        // swap16: x <- [x.r0, y.r0, x.r2, y.r2], y <- [x.r1, y.r1, x.r3, y.r3] with y = -x
+        const int row = l / 16, li = l % 16;
+        const double sx = (row % 2 == 0) ? hin[l] : -hin[(row - 1) * 16 + li];
+        const double sy = (row % 2 == 0) ? hin[(row + 1) * 16 + li] : -hin[l];
+        if (hout[256 + l] != sx || hout[320 + l] != sy) ++bad;
+        // swap32: x <- [x.lo, y.lo], y <- [x.hi, y.hi]
+        const double tx = (l < 32) ? hin[l] : -hin[l - 32];
+        const double ty = (l < 32) ? hin[l + 32] : -hin[l];
+        if (hout[384 + l] != tx || hout[448 + l] != ty) ++bad;
+        // grouped row sums over lanes {l mod 8 + 8q} (8x8) and {l mod 8 + 8q} within 32-lane halves (8x4)
+        const double f8[6] = {1.0, 2.0, 3.0, -1.0, 0.5, 7.0};
+        for (int j = 0; j < 6; ++j)
+            if (std::fabs(hout[512 + 64 * j + l] - f8[j] * ss) > 1e-12 * std::fabs(f8[j] * ss)) ++bad;
+        double s4 = 0.0;
+        for (int q = 0; q < 4; ++q) s4 += hin[(l & 7) + 8 * q + (l & 32)];
+        const double f4[4] = {1.0, -2.0, 3.0, 0.25};
+        for (int j = 0; j < 4; ++j)
+            if (std::fabs(hout[896 + 64 * j + l] - f4[j] * s4) > 1e-12 * std::fabs(f4[j] * s4)) ++bad;
     }
     *failures = bad;
     return GBS_OK;

@@ -99,6 +99,23 @@ __device__ __forceinline__ double swap_sum32(double x) {
     return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
 }
 
+// Register swaps across rows (16 lanes) and halves (32 lanes), gfx950:
+//   swap16(x, y): x <- [x.r0, y.r0, x.r2, y.r2], y <- [x.r1, y.r1, x.r3, y.r3]
+//   swap32(x, y): x <- [x.lo, y.lo],             y <- [x.hi, y.hi]
+// (rK = lanes 16K..16K+15, lo/hi = lanes 0..31 / 32..63; checked by gbs_selftest).
+__device__ __forceinline__ void swap16(double& x, double& y) {
+    auto l = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false, false);
+    auto h = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false, false);
+    x = __hiloint2double((int)h[0], (int)l[0]);
+    y = __hiloint2double((int)h[1], (int)l[1]);
+}
+__device__ __forceinline__ void swap32(double& x, double& y) {
+    auto l = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false, false);
+    auto h = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false, false);
+    x = __hiloint2double((int)h[0], (int)l[0]);
+    y = __hiloint2double((int)h[1], (int)l[1]);
+}
+
 // Sum over the 8 lanes {l mod 8 + 8 q : q = 0..7}.
 __device__ __forceinline__ double sum_stride8(double x) {
     x += dpp_mov<0x128>(x);  // row_ror:8 -> partner lane l ^ 8
@@ -181,6 +198,102 @@ __device__ __forceinline__ double sum_rows(double x) {
         x = swap_sum16(x);
     }
     return x;
+}
+
+// Row sums of NV values at once.  Where a level crosses rows or halves
+// (permlane swaps), values travel in pairs: each swap level leaves every lane
+// with half of the values summed over its partner (reduce-scatter), the
+// in-row level is a DPP butterfly, and the same swaps run backwards to hand
+// every lane all NV totals (all-gather).  Each total is formed in one place
+// and copied, so all Q lanes end with the same bits.
+template <int P, int Q, int NV>
+__device__ __forceinline__ void rowsum_many(double (&v)[NV]) {
+    static_assert(NV % 2 == 0, "even number of values");
+    if constexpr (P == 8 && Q == 8) {
+        constexpr int NA = NV / 2, NB = (NA + 1) / 2;
+        double a[NA], b[NB];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+            double x = v[2 * j], y = v[2 * j + 1];
+            swap32(x, y);
+            a[j] = x + y;  // lanes 0..31: total of v[2j]; lanes 32..63: of v[2j+1]
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            double x = a[2 * j], y = (2 * j + 1 < NA) ? a[2 * j + 1] : 0.0;
+            swap16(x, y);
+            b[j] = x + y;  // even rows: a[2j], odd rows: a[2j+1]
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) b[j] += dpp_mov<0x128>(b[j]);  // row_ror:8 (lane ^ 8)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            double x = b[j], y = b[j];
+            swap16(x, y);
+            a[2 * j] = x;
+            if (2 * j + 1 < NA) a[2 * j + 1] = y;
+        }
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+            double x = a[j], y = a[j];
+            swap32(x, y);
+            v[2 * j] = x;
+            v[2 * j + 1] = y;
+        }
+    } else if constexpr (P == 8 && Q == 4) {
+        constexpr int NB = NV / 2;
+        double b[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            double x = v[2 * j], y = v[2 * j + 1];
+            swap16(x, y);
+            b[j] = x + y;
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) b[j] += dpp_mov<0x128>(b[j]);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            double x = b[j], y = b[j];
+            swap16(x, y);
+            v[2 * j] = x;
+            v[2 * j + 1] = y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = sum_rows<P, Q>(v[j]);
+    }
+}
+
+// Right application of a reflector: u_i = sum_k a[i][k] vc[k] for every local
+// row, and the border-row product sum_k y[k] vc[k], reduced together.
+template <int P, int Q, int MR, int MC, int K0>
+__device__ __forceinline__ void right_apply(double2 (&a)[MR][MC], double2 (&y)[MC], const double2 (&vc)[MC]) {
+    double v[2 * MR + 2];
+#pragma unroll
+    for (int i = 0; i < MR; ++i) {
+        double2 u = cz();
+#pragma unroll
+        for (int k = K0; k < MC; ++k) u = cfma(a[i][k], vc[k], u);
+        v[2 * i] = u.x;
+        v[2 * i + 1] = u.y;
+    }
+    {
+        double2 sy = cz();
+#pragma unroll
+        for (int k = K0; k < MC; ++k) sy = cfma(y[k], vc[k], sy);
+        v[2 * MR] = sy.x;
+        v[2 * MR + 1] = sy.y;
+    }
+    rowsum_many<P, Q, 2 * MR + 2>(v);
+#pragma unroll
+    for (int i = 0; i < MR; ++i) {
+        const double2 u = make_double2(v[2 * i], v[2 * i + 1]);
+#pragma unroll
+        for (int k = K0; k < MC; ++k) a[i][k] = cfms_cb(u, vc[k], a[i][k]);
+    }
+    const double2 sy = make_double2(v[2 * MR], v[2 * MR + 1]);
+#pragma unroll
+    for (int k = K0; k < MC; ++k) y[k] = cfms_cb(sy, vc[k], y[k]);
 }
 
 template <int P>
@@ -291,21 +404,7 @@ __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC
             }
         }
         // right: H <- H (I - v v^H); border row y^T <- y^T (I - v v^H)
-#pragma unroll
-        for (int i = 0; i < MR; ++i) {
-            double2 u = cz();
-#pragma unroll
-            for (int k = KJ; k < MC; ++k) u = cfma(a[i][k], vc[k], u);
-            u = csum_rows<P, Q>(u);
-#pragma unroll
-            for (int k = KJ; k < MC; ++k) a[i][k] = cfms_cb(u, vc[k], a[i][k]);
-        }
-        double2 sy = cz();
-#pragma unroll
-        for (int k = KJ; k < MC; ++k) sy = cfma(y[k], vc[k], sy);
-        sy = csum_rows<P, Q>(sy);
-#pragma unroll
-        for (int k = KJ; k < MC; ++k) y[k] = cfms_cb(sy, vc[k], y[k]);
+        right_apply<P, Q, MR, MC, KJ>(a, y, vc);
     }
 }
 
@@ -322,36 +421,45 @@ __device__ __forceinline__ void hess_all(double2 (&a)[MR][MC], double2 (&y)[MC],
 // One La Budde step (team-local): row r = rho + 1 of H' is in rowbuf at
 // index rho + k for H'[r][r + k]; sub_in = H'[r + 1][r].  Team lane d updates
 // coefficient d of the trailing polynomial of rows r.. (ring slot r % RS).
-__device__ __forceinline__ void labudde_step(int rho, int m, int D, int d, double2 hrr, double2 sub_in, double2& pik,
-                                             const double2* __restrict__ rowbuf, double2* __restrict__ betab,
-                                             double2* __restrict__ ring) {
+// With split = 2 (64-lane team, D + 1 <= 32) the lanes d and d + 32 share
+// coefficient d: the low half takes odd k, the high half even k, and the two
+// partial sums are added across the halves.
+__device__ __forceinline__ void labudde_step(int rho, int m, int D, int d, int half, int split, double2 hrr,
+                                             double2 sub_in, double2& pik, const double2* __restrict__ rowbuf,
+                                             double2* __restrict__ betab, double2* __restrict__ ring) {
     const int RS = D + 1;
     const int r = rho + 1;
     // pi_{r,k} = H'[r+1][r] pi_{r+1,k-1} (lane shift by one), pi_{r,0} = 1
     const double2 sh = make_double2(dpp_mov<0x138>(pik.x), dpp_mov<0x138>(pik.y));  // wave_shr:1
     pik = (d == 0) ? make_double2(1.0, 0.0) : cmul(sub_in, sh);
     const int K = min(D - 1, m - rho - 1);
-    if (d >= 1 && d <= K) betab[d] = cmul(rowbuf[rho + d], pik);
+    if (half == 0 && d >= 1 && d <= K) betab[d] = cmul(rowbuf[rho + d], pik);
     wave_sync();
+    double2 e = cz();
     if (d <= D) {
         const double2* prev = ring + ((r + 1) % RS) * RS;
-        double2 e = prev[d];
-        if (d >= 1) e = cfms(hrr, prev[d - 1], e);
+        if (half == 0) {
+            e = prev[d];
+            if (d >= 1) e = cfms(hrr, prev[d - 1], e);
+        }
         const int kmax = min(K, d - 1);
         // element of poly r+k+1 at coefficient d-k-1: ring[slot(k) * RS + d - k - 1]
-        int slot = (r + 2) % RS;
+        int slot = (r + 2 + half) % RS;
         const double2* base = ring + d - 1;
-        for (int k = 1; k <= kmax; ++k) {
+        for (int k = 1 + half; k <= kmax; k += split) {
             e = cfms(betab[k], base[slot * RS - k], e);
-            slot = (slot + 1 == RS) ? 0 : slot + 1;
+            slot += split;
+            if (slot >= RS) slot -= RS;
         }
-        ring[(r % RS) * RS + d] = e;
     }
+    if (split == 2) e = make_double2(swap_sum32(e.x), swap_sum32(e.y));
+    if (half == 0 && d <= D) ring[(r % RS) * RS + d] = e;
     wave_sync();
 }
 
 template <int P, int Q, int MR, int MC, int I>
-__device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, int D, int d, int pr, int pc,
+__device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, int D, int d, int half, int split,
+                                             int pr, int pc,
                                              bool row_owner_group, double2* __restrict__ rowbuf_own,
                                              const double2* __restrict__ rowbuf, double2* __restrict__ betab,
                                              double2* __restrict__ ring, double2& pik, double2& sub) {
@@ -366,11 +474,11 @@ __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, 
             wave_sync();
             const double2 hrr = rowbuf[rho];
             const double2 sub_next = (rho >= 1) ? rowbuf[rho - 1] : cz();
-            labudde_step(rho, m, D, d, hrr, sub, pik, rowbuf, betab, ring);
+            labudde_step(rho, m, D, d, half, split, hrr, sub, pik, rowbuf, betab, ring);
             sub = sub_next;
         }
-        labudde_rows<P, Q, MR, MC, I - 1>(a, m, D, d, pr, pc, row_owner_group, rowbuf_own, rowbuf, betab, ring, pik,
-                                          sub);
+        labudde_rows<P, Q, MR, MC, I - 1>(a, m, D, d, half, split, pr, pc, row_owner_group, rowbuf_own, rowbuf,
+                                          betab, ring, pik, sub);
     }
 }
 
@@ -488,21 +596,7 @@ __global__ void __launch_bounds__(64) charpoly_kernel(const double2* __restrict_
 #pragma unroll
             for (int i = 0; i < MR; ++i) a[i][k] = cfms(vr[i], w, a[i][k]);
         }
-#pragma unroll
-        for (int i = 0; i < MR; ++i) {
-            double2 u = cz();
-#pragma unroll
-            for (int k = 0; k < MC; ++k) u = cfma(a[i][k], vc[k], u);
-            u = csum_rows<P, Q>(u);
-#pragma unroll
-            for (int k = 0; k < MC; ++k) a[i][k] = cfms_cb(u, vc[k], a[i][k]);
-        }
-        double2 sy = cz();
-#pragma unroll
-        for (int k = 0; k < MC; ++k) sy = cfma(y[k], vc[k], sy);
-        sy = csum_rows<P, Q>(sy);
-#pragma unroll
-        for (int k = 0; k < MC; ++k) y[k] = cfms_cb(sy, vc[k], y[k]);
+        right_apply<P, Q, MR, MC, 0>(a, y, vc);
     }
     if (lane % G == 0) nb[1] = alpha;
 
@@ -512,7 +606,9 @@ __global__ void __launch_bounds__(64) charpoly_kernel(const double2* __restrict_
     // La Budde over the trailing blocks of H' (size m + 1).  Team t of T lanes
     // handles group t + NT * pass; lane d of the team holds coefficient d.
     const int team = lane / T;
-    const int d = lane % T;
+    const int split = (T == 64 && D + 1 <= 32) ? 2 : 1;
+    const int d = lane % (T / split);
+    const int half = (lane % T) / (T / split);
     const int Mp = m + 1;
     for (int pass = 0; pass < W / NT; ++pass) {
         const int gt = pass * NT + team;          // group served by my team
@@ -521,11 +617,12 @@ __global__ void __launch_bounds__(64) charpoly_kernel(const double2* __restrict_
         double2* rowbuf = L.rowbuf + team * 64;
         double2* betab = L.betab + team * 64;
         double2* ring = L.ring + team * RS * RS;
-        if (d < RS) ring[(Mp % RS) * RS + d] = (d == 0) ? make_double2(1.0, 0.0) : cz();
+        if (half == 0 && d < RS) ring[(Mp % RS) * RS + d] = (d == 0) ? make_double2(1.0, 0.0) : cz();
         double2 pik = (d == 0) ? make_double2(1.0, 0.0) : cz();
         double2 sub = cz();
         wave_sync();
-        labudde_rows<P, Q, MR, MC, MR - 1>(a, m, D, d, pr, pc, own, rowbuf_own, rowbuf, betab, ring, pik, sub);
+        labudde_rows<P, Q, MR, MC, MR - 1>(a, m, D, d, half, split, pr, pc, own, rowbuf_own, rowbuf, betab, ring,
+                                           pik, sub);
         // border row: H'[0][k] = y''_{k-1}, H'[0][0] = 0, H'[1][0] = alpha
         if (own && pr == 0) {
 #pragma unroll
@@ -533,9 +630,9 @@ __global__ void __launch_bounds__(64) charpoly_kernel(const double2* __restrict_
         }
         wave_sync();
         const double2 alpha_t = L.misc[gt * 2 + 1];
-        labudde_step(-1, m, D, d, cz(), alpha_t, pik, rowbuf, betab, ring);
+        labudde_step(-1, m, D, d, half, split, cz(), alpha_t, pik, rowbuf, betab, ring);
         const uint64_t gi = first + gt;
-        if (d <= D && gi < count) {
+        if (half == 0 && d <= D && gi < count) {
             double2* out = Eout + gi * (uint64_t)(2 * RS);
             out[d] = ring[(1 % RS) * RS + d];
             out[RS + d] = ring[d];

@@ -226,6 +226,21 @@ __global__ void __launch_bounds__(64) selftest_kernel(const double* __restrict__
     out[64 + l] = sum_stride8(x);
     out[128 + l] = readlane_d(x, 37);
     out[192 + l] = dpp_mov<0x138>(x);
+    double a = x, b = -x;
+    swap16(a, b);
+    out[256 + l] = a;
+    out[320 + l] = b;
+    a = x;
+    b = -x;
+    swap32(a, b);
+    out[384 + l] = a;
+    out[448 + l] = b;
+    double v[6] = {x, 2.0 * x, 3.0 * x, -x, 0.5 * x, 7.0 * x};
+    rowsum_many<8, 8, 6>(v);
+    for (int j = 0; j < 6; ++j) out[512 + 64 * j + l] = v[j];
+    double w[4] = {x, -2.0 * x, 3.0 * x, 0.25 * x};
+    rowsum_many<8, 4, 4>(w);
+    for (int j = 0; j < 4; ++j) out[896 + 64 * j + l] = w[j];
 }
 
 // ---------------------------------------------------------------- launchers
