@@ -68,6 +68,79 @@ def cpu_baseline(A, N, seconds):
     }
 
 
+def bench_batch(args, gbs):
+    """One step = one replay of the captured batch plan over all items."""
+    import numpy as np
+    import torch
+
+    from paper_2010_15595_amd import workloads
+
+    st = workloads.config4(count=args.batch_count)
+    mats = [gbs.expand(st["B"], st["gamma"], pat) for pat in st["patterns"]]
+    dims = [a.shape[0] for a in mats]
+    prec = gbs.GBS_FP64 if args.precision == "fp64" else gbs.GBS_FP32_COMP
+    torch.cuda.set_device(0)
+    gbs.init(0)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    plan = gbs.BatchPlan(dims, prec=prec, autotune=not args.no_autotune)
+    info = plan.info()
+    log(f"plan ({time.perf_counter() - t0:.2f} s): {info}")
+    packed = torch.from_numpy(gbs.pack(mats)).to(dev)
+    out = torch.zeros(len(mats), dtype=torch.complex128, device=dev)
+    ab = torch.zeros(len(mats), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        plan.run(packed, out, ab, stream)
+    torch.cuda.synchronize()
+    ref_out = out.cpu().numpy().copy()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.run(packed, out, ab, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    gpu_ms = ev0.elapsed_time(ev1)
+    res = out.cpu().numpy()
+    if args.warmup > 0 and not np.array_equal(res, ref_out):
+        log("WARNING: batch results changed between replays")
+    sec = gpu_ms / 1000.0
+    items_per_s = args.steps * len(mats) / sec
+    terms_per_s = args.steps * info["subset_terms"] / sec
+    flops_per_s = args.steps * info["yardstick_flops"] / sec
+    log(f"{args.steps} replays in {gpu_ms:.1f} ms: {items_per_s:.1f} lhaf/s, {terms_per_s:.4e} subset-terms/s, "
+        f"{flops_per_s / 1e12:.2f} yardstick TFLOP/s")
+    result = {
+        "metric": "loop hafnians/s and subset-terms/s, batched uneven N",
+        "value": items_per_s,
+        "unit": "lhaf/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if args.precision == "fp64" else "c128 Hessenberg + c64 La Budde/series (compensated)",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{len(mats)} loop hafnians of uneven even N in [10, 36] expanded from one 100-mode pure "
+                        "state (r=1.0, sigma=0.2), chain-like photon patterns; one HIP graph replay per step",
+            "items": len(mats),
+            "subset_terms_per_step": info["subset_terms"],
+            "tile_subsets": info["tile_subsets"],
+            "graph_kernel_nodes": info["kernel_nodes"],
+            "rounds": info["rounds"],
+        },
+        "subset_terms_per_s": terms_per_s,
+        "yardstick_tflops": flops_per_s / 1e12,
+        "pct_fp64_peak": 100.0 * flops_per_s / (FP64_PEAK_TFLOPS * 1e12),
+    }
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,10 +149,16 @@ def main():
     ap.add_argument("--N", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "fp32comp"], default="fp64",
+                    help="fp32comp: La Budde, series and per-lane sums in complex FP32 (Hessenberg FP64)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the lane-grid autotuner (use the heuristic or GBS_AUTOTUNE_CACHE)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--workload", choices=["n50", "batch"], default="n50",
+                    help="batch: 4096 loop hafnians of uneven N in [10, 36] from one 100-mode state, "
+                         "one captured graph of persistent launches per step")
+    ap.add_argument("--batch-count", type=int, default=4096)
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -110,6 +189,9 @@ def main():
         libbuild.build()
     import paper_2010_15595_amd as gbs
 
+    if args.workload == "batch":
+        return bench_batch(args, gbs)
+
     N = args.N
     st = workload(N)
     A = gbs.expand(st["B"], st["gamma"], st["pattern"])
@@ -118,6 +200,7 @@ def main():
     terms = float(1 << n)
     flops = gbs.yardstick_flops(N)
 
+    prec = gbs.GBS_FP64 if args.precision == "fp64" else gbs.GBS_FP32_COMP
     torch.cuda.set_device(0)
     gbs.init(0)
     dev = torch.device("cuda:0")
@@ -134,7 +217,7 @@ def main():
         log(f"autotune n={n} ({time.perf_counter() - t0:.2f} s): " + " ".join(f"{s}:{lay}" for s, lay in tuned.items()))
     log(f"warmup {args.warmup} step(s), N={N} ({int(terms)} subsets/step) ...")
     for _ in range(args.warmup):
-        gbs.lhaf_device(A_dev, out, ab, stream)
+        gbs.lhaf_device(A_dev, out, ab, stream, prec)
     torch.cuda.synchronize()
     ref_val = complex(out.cpu().numpy()[0])
 
@@ -146,7 +229,7 @@ def main():
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        gbs.lhaf_device(A_dev, out, ab, stream)
+        gbs.lhaf_device(A_dev, out, ab, stream, prec)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -176,7 +259,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128",
+        "dtype": "c128" if args.precision == "fp64" else "c128 Hessenberg + c64 La Budde/series (compensated)",
         "data": "synthetic",
         "config": {
             "workload": f"loop hafnian N={N} of a 100-mode pure Gaussian state (Haar U, r=1.2, sigma=0.1), "

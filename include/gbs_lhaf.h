@@ -53,7 +53,9 @@ typedef enum {
 
 typedef enum {
     GBS_FP64 = 0,      /* all steps in IEEE binary64 */
-    GBS_FP32_COMP = 1  /* reserved: complex FP32 subset terms, FP64 reduction */
+    GBS_FP32_COMP = 1  /* Hessenberg reduction and all cross-lane / final sums in
+                          binary64; La Budde, power-trace series and the per-lane
+                          compensated (TwoSum) sums in complex binary32 */
 } gbs_precision;
 
 /* Optional diagnostics of one loop-hafnian evaluation. */
@@ -139,6 +141,47 @@ gbs_status gbs_lhaf_terms(const gbs_z *A, int32_t N, int64_t lda, const uint64_t
  * `stream` (a hipStream_t, NULL = null stream); asynchronous. */
 gbs_status gbs_lhaf_device(const gbs_z *A_dev, int32_t N, gbs_precision prec, gbs_z *out_dev,
                            double *abs_sum_dev, void *stream);
+
+/* ---- batches of loop hafnians: plan once, replay many times -------------- */
+
+typedef struct gbs_plan gbs_plan;
+
+typedef struct {
+    int32_t items;           /* loop hafnians per run                             */
+    int32_t tiles;           /* work tiles (runs of subsets of one size class)    */
+    int32_t rounds;          /* rounds over the two coefficient buffers           */
+    int32_t kernel_nodes;    /* kernel launches captured in the graph             */
+    int64_t subset_terms;    /* sum over items of 2^n_i                           */
+    int64_t tile_subsets;    /* subsets per tile (autotuned or default)           */
+    int64_t workspace_bytes; /* device memory owned by the plan                   */
+    double yardstick_flops;  /* flop yardstick of one run (gbs_yardstick_flops)   */
+    double tune_ms;          /* time of the fastest tile size when autotuned     */
+} gbs_batch_info;
+
+#define GBS_PLAN_AUTOTUNE 1
+
+/* Plans a batch of `count` loop hafnians of dimensions dims[i] <= GBS_MAX_DIM
+ * (the conditional-sampling chain of the paper's Sec. III produces such
+ * batches: many loop hafnians of uneven size).  The input of a run is the
+ * packed concatenation of the matrices: item i is an N_i x N_i row-major
+ * block (diagonal = loop weights) at element offset sum_{j<i} N_j^2.  The plan
+ * splits every item's subset sum into tiles (runs of subsets of one size
+ * class), processes them with persistent per-subset kernels that take tiles
+ * largest first from a device counter, then the series kernels and a
+ * fixed-order compensated reduction per item; the whole schedule is captured
+ * once into a HIP graph.  flags = GBS_PLAN_AUTOTUNE times candidate tile sizes
+ * and the lane grid of every n in the batch on the device and keeps the
+ * fastest.  Owns its device workspace until gbs_batch_plan_destroy. */
+gbs_status gbs_batch_plan_create(const int32_t *dims, int32_t count, gbs_precision prec, int32_t flags,
+                                 gbs_plan **plan);
+gbs_status gbs_batch_plan_info(const gbs_plan *plan, gbs_batch_info *info);
+/* Runs the plan: mats_dev packed inputs (device memory), out_dev[count]
+ * results and abs_sum_dev[count] (sum_S |t_S|, nullable), both device memory.
+ * Ordered on `stream` (hipStream_t, NULL = null stream); asynchronous.  Runs
+ * of one plan must not overlap. */
+gbs_status gbs_batch_run(gbs_plan *plan, const gbs_z *mats_dev, gbs_z *out_dev, double *abs_sum_dev,
+                         void *stream);
+void gbs_batch_plan_destroy(gbs_plan *plan);
 
 /* ---- kernel layout selection and autotuning ------------------------------ */
 

@@ -6,6 +6,7 @@ probability of Sec. II, Eq. (12), computed by hand-written HIP kernels behind
 the C ABI of include/gbs_lhaf.h.  This package is the thin Python binding.
 """
 from ._lib import (  # noqa: F401
+    BatchPlan,
     GBS_FP32_COMP,
     GBS_FP64,
     GbsError,
@@ -19,6 +20,7 @@ from ._lib import (  # noqa: F401
     lhaf_terms,
     lib,
     max_dim,
+    pack,
     probability,
     profile_enable,
     profile_read,

@@ -44,6 +44,12 @@ class gbs_tune_report(ctypes.Structure):
 LAYOUTS = {0: "4x4", 1: "8x4", 2: "8x8"}
 
 
+class gbs_batch_info(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_int32), ("tiles", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("kernel_nodes", ctypes.c_int32), ("subset_terms", ctypes.c_int64), ("tile_subsets", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("yardstick_flops", ctypes.c_double), ("tune_ms", ctypes.c_double)]
+
+
 class gbs_profile(ctypes.Structure):
     _fields_ = [("charpoly_ms", ctypes.c_double), ("series_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double),
                 ("charpoly_launches", ctypes.c_int64), ("series_launches", ctypes.c_int64),
@@ -111,6 +117,15 @@ def lib():
         L.gbs_set_layout.restype = st
         L.gbs_autotune.argtypes = [ctypes.c_int32, ctypes.POINTER(gbs_tune_report)]
         L.gbs_autotune.restype = st
+        L.gbs_batch_plan_create.argtypes = [I32P, ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_void_p)]
+        L.gbs_batch_plan_create.restype = st
+        L.gbs_batch_plan_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(gbs_batch_info)]
+        L.gbs_batch_plan_info.restype = st
+        L.gbs_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.gbs_batch_run.restype = st
+        L.gbs_batch_plan_destroy.argtypes = [ctypes.c_void_p]
+        L.gbs_batch_plan_destroy.restype = None
         L.gbs_yardstick_flops.argtypes = [ctypes.c_int32]
         L.gbs_yardstick_flops.restype = ctypes.c_double
         _L = L
@@ -273,3 +288,55 @@ def autotune(n):
         times = {LAYOUTS[k]: r.ns_per_subset[s][k] for k in range(3) if r.ns_per_subset[s][k] > 0}
         out[s] = (LAYOUTS[r.layout[s]], times)
     return out
+
+
+def pack(mats):
+    """Packed batch input: the matrices' row-major blocks concatenated."""
+    flat = [np.ascontiguousarray(np.asarray(a, dtype=np.complex128)).ravel() for a in mats]
+    return np.concatenate(flat) if flat else np.zeros(0, dtype=np.complex128)
+
+
+class BatchPlan:
+    """A captured schedule for a batch of loop hafnians of the given
+    dimensions (gbs_batch_plan_create); run() replays it on a stream."""
+
+    def __init__(self, dims, prec=GBS_FP64, autotune=False):
+        d = np.ascontiguousarray(dims, dtype=np.int32)
+        self.count = int(d.shape[0])
+        h = ctypes.c_void_p()
+        _check(lib().gbs_batch_plan_create(d.ctypes.data_as(I32P), self.count, prec, 1 if autotune else 0,
+                                           ctypes.byref(h)))
+        self._h = h
+
+    def info(self):
+        i = gbs_batch_info()
+        _check(lib().gbs_batch_plan_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in gbs_batch_info._fields_}
+
+    def run(self, mats_dev, out, abs_sum=None, stream=None):
+        """mats_dev: packed complex128 device tensor; out: complex128 device
+        tensor of length count; abs_sum: float64 device tensor or None."""
+        import torch
+
+        if mats_dev.dtype != torch.complex128 or not mats_dev.is_cuda or not mats_dev.is_contiguous():
+            raise ValueError("mats_dev must be a contiguous complex128 device tensor")
+        if out.dtype != torch.complex128 or not out.is_cuda or out.numel() < self.count:
+            raise ValueError("out must be a complex128 device tensor with one entry per item")
+        if abs_sum is not None and (abs_sum.dtype != torch.float64 or not abs_sum.is_cuda):
+            raise ValueError("abs_sum must be a float64 device tensor")
+        if stream is None:
+            stream = torch.cuda.current_stream(out.device)
+        _check(lib().gbs_batch_run(self._h, ctypes.c_void_p(mats_dev.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(abs_sum.data_ptr()) if abs_sum is not None else None,
+                                   ctypes.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gbs_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -18,7 +18,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result",
 ]
-SOURCES = ["charpoly_l88.hip", "charpoly_l84.hip", "charpoly_l44.hip", "lhaf_kernels.hip", "gbs_host.cpp"]
+SOURCES = ["charpoly_l88.hip", "charpoly_l84.hip", "charpoly_l44.hip", "lhaf_kernels.hip", "gbs_host.cpp", "gbs_batch.cpp"]
 
 
 def _compile(src):

@@ -1,0 +1,490 @@
+// Batched loop hafnians (C ABI gbs_batch_*): a plan splits the subset sums of
+// many loop hafnians of uneven size into tiles, assigns them to rounds over two
+// alternating coefficient buffers, and captures the whole schedule into one
+// HIP graph:
+//
+//   fill counters -> prep all items
+//   round r: one persistent per-subset launch per kernel instance (parallel
+//            graph branches; each waits for the series of round r-2, which
+//            read the same buffer) -> series launches per n
+//   per-item fixed-order compensated reduction
+//
+// Tiles within a launch are ordered largest first, so the device counter
+// hands out long work first (longest-processing-time schedule).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <vector>
+
+#include "gbs_internal.h"
+
+using namespace gbs_host;
+
+namespace {
+
+constexpr int kSeriesPerThread = 8;                   // subsets per lane in the series kernel
+constexpr int kSeriesBlock = 64 * kSeriesPerThread;   // subsets per series block
+constexpr int kBranches = 4;                          // parallel graph branches per round
+constexpr int kPersistentWaves = 256 * 8;             // wavefronts of a persistent launch
+
+struct CharpolyLaunch {
+    int round, layout, s_rep, inst;
+    int tile_begin, ntiles;  // range in the device tile array
+    int counter;
+};
+
+struct SeriesLaunch {
+    int round, n;
+    int block_begin, nblocks;
+};
+
+}  // namespace
+
+struct gbs_plan {
+    int device = 0;
+    int count = 0;
+    bool fp32 = false;
+    int64_t tile_subsets = 0;
+    int rounds = 0;
+    int64_t subset_terms = 0;
+    double flops = 0.0;
+    double tune_ms = 0.0;
+    int64_t in_elems = 0;
+    size_t bytes = 0;
+    int max_n = 0;
+    std::vector<CharpolyLaunch> cp;
+    std::vector<SeriesLaunch> se;
+    int ntiles = 0;
+    // device memory
+    double2* staging = nullptr;   // packed input copy
+    double2* a0 = nullptr;        // per-item A0 blocks
+    double2* dv = nullptr;        // per-item loop weights
+    gbs::BatchItem* items = nullptr;
+    int64_t* in_off = nullptr;
+    int* dims = nullptr;
+    gbs::BatchTile* tiles = nullptr;
+    gbs::SeriesBlock* sblocks = nullptr;
+    int64_t* pbeg = nullptr;
+    double* partials = nullptr;
+    unsigned* counters = nullptr;
+    void* ebuf[2] = {nullptr, nullptr};
+    double2* out = nullptr;
+    double* abs = nullptr;
+    hipStream_t cs = nullptr;
+    hipStream_t br[kBranches] = {};
+    std::vector<hipEvent_t> events;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+};
+
+namespace {
+
+void plan_free(gbs_plan* p) {
+    if (!p) return;
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    for (hipEvent_t e : p->events) hipEventDestroy(e);
+    if (p->t0) hipEventDestroy(p->t0);
+    if (p->t1) hipEventDestroy(p->t1);
+    for (hipStream_t s : p->br)
+        if (s) hipStreamDestroy(s);
+    if (p->cs) hipStreamDestroy(p->cs);
+    void* bufs[] = {p->staging, p->a0,       p->dv,       p->items,   p->in_off, p->dims,    p->tiles,
+                    p->sblocks, p->pbeg,     p->partials, p->counters, p->ebuf[0], p->ebuf[1], p->out,
+                    p->abs};
+    for (void* b : bufs)
+        if (b) hipFree(b);
+    delete p;
+}
+
+template <class T>
+gbs_status upload(T** dst, const std::vector<T>& src, size_t* bytes) {
+    const size_t nb = std::max<size_t>(1, src.size()) * sizeof(T);
+    hipError_t e = hipMalloc((void**)dst, nb);
+    if (e != hipSuccess) return fail(GBS_E_NOMEM, "hipMalloc(%zu) failed: %s", nb, hipGetErrorString(e));
+    *bytes += nb;
+    if (!src.empty()) HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return GBS_OK;
+}
+
+gbs_status dmalloc(void** dst, size_t nb, size_t* bytes) {
+    nb = std::max<size_t>(nb, 16);
+    hipError_t e = hipMalloc(dst, nb);
+    if (e != hipSuccess) return fail(GBS_E_NOMEM, "hipMalloc(%zu) failed: %s", nb, hipGetErrorString(e));
+    *bytes += nb;
+    return GBS_OK;
+}
+
+// Builds schedule, buffers and graph for one tile size into p (freed by the
+// caller on failure).
+gbs_status plan_build_into(DevCtx* c, const std::vector<int>& dims, bool fp32, int64_t tile_subsets,
+                           int64_t round_bytes, gbs_plan* p) {
+    p->device = c->device;
+    p->count = (int)dims.size();
+    p->fp32 = fp32;
+    p->tile_subsets = tile_subsets;
+    const size_t vbytes = fp32 ? sizeof(float2) : sizeof(double2);
+    const int nitems = p->count;
+
+    // items
+    std::vector<int64_t> in_off(nitems), a0_off(nitems), d_off(nitems);
+    std::vector<int> npair(nitems);
+    int64_t ia = 0, iin = 0, id = 0;
+    for (int i = 0; i < nitems; ++i) {
+        const int N = dims[i], Np = N + (N & 1);
+        npair[i] = Np / 2;
+        in_off[i] = iin;
+        a0_off[i] = ia;
+        d_off[i] = id;
+        iin += (int64_t)N * N;
+        ia += (int64_t)Np * Np;
+        id += Np;
+        p->max_n = std::max(p->max_n, Np / 2);
+        p->subset_terms += (int64_t)1 << (Np / 2);
+        p->flops += gbs_yardstick_flops(N);
+    }
+    p->in_elems = iin;
+
+    // tiles: (item, s, rank range); series blocks and partial ranges per item
+    struct HostTile {
+        gbs::BatchTile t;
+        int inst, layout;
+        double cost;
+        int round;
+    };
+    std::vector<HostTile> ht;
+    for (int i = 0; i < nitems; ++i) {
+        const int n = npair[i];
+        for (int s = 1; s <= n; ++s) {
+            const uint64_t cnt = binom_host(n, s);
+            const int lay = layout_for(c, n, s);
+            for (uint64_t r0 = 0; r0 < cnt; r0 += (uint64_t)tile_subsets) {
+                HostTile h{};
+                h.t.rank0 = r0;
+                h.t.count = std::min<uint64_t>((uint64_t)tile_subsets, cnt - r0);
+                h.t.item = i;
+                h.t.s = s;
+                h.layout = lay;
+                h.inst = gbs::charpoly_instance(lay, s);
+                h.cost = subset_flops(n, s) * (double)h.t.count;
+                ht.push_back(h);
+            }
+        }
+    }
+    // partials: per item contiguous, in (item, s, rank) order
+    std::vector<int64_t> pbeg(nitems + 1, 0);
+    std::vector<int64_t> tile_pidx(ht.size());
+    {
+        int64_t pi = 0;
+        size_t k = 0;
+        for (int i = 0; i < nitems; ++i) {
+            pbeg[i] = pi;
+            while (k < ht.size() && ht[k].t.item == i) {
+                tile_pidx[k] = pi;
+                pi += (int64_t)((ht[k].t.count + kSeriesBlock - 1) / kSeriesBlock);
+                ++k;
+            }
+        }
+        pbeg[nitems] = pi;
+    }
+    // rounds: tiles in decreasing cost, filled up to round_bytes of coefficients
+    std::vector<size_t> order(ht.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return ht[a].cost > ht[b].cost; });
+    std::vector<int64_t> round_fill;
+    for (size_t k : order) {
+        const int64_t need = (int64_t)ht[k].t.count * 2 * (npair[ht[k].t.item] + 2) * (int64_t)vbytes;
+        int r = (int)round_fill.size() - 1;
+        if (r < 0 || round_fill[r] + need > round_bytes) {
+            round_fill.push_back(0);
+            r = (int)round_fill.size() - 1;
+        }
+        ht[k].t.eoff = (uint64_t)(round_fill[r] / (int64_t)vbytes);
+        round_fill[r] += need;
+        ht[k].round = r;
+    }
+    p->rounds = (int)round_fill.size();
+    const int64_t ebuf_bytes = round_fill.empty() ? 16 : *std::max_element(round_fill.begin(), round_fill.end());
+
+    // device tile array: grouped by (round, instance), largest first inside a group
+    std::vector<size_t> dorder(order);
+    std::stable_sort(dorder.begin(), dorder.end(), [&](size_t a, size_t b) {
+        if (ht[a].round != ht[b].round) return ht[a].round < ht[b].round;
+        return ht[a].inst < ht[b].inst;  // stable: cost order kept inside
+    });
+    std::vector<gbs::BatchTile> dtiles(dorder.size());
+    std::vector<int> pos_of(ht.size());
+    for (size_t q = 0; q < dorder.size(); ++q) {
+        dtiles[q] = ht[dorder[q]].t;
+        pos_of[dorder[q]] = (int)q;
+    }
+    for (size_t q = 0; q < dorder.size();) {
+        size_t e = q;
+        while (e < dorder.size() && ht[dorder[e]].round == ht[dorder[q]].round &&
+               ht[dorder[e]].inst == ht[dorder[q]].inst)
+            ++e;
+        const HostTile& h = ht[dorder[q]];
+        p->cp.push_back(CharpolyLaunch{h.round, h.layout, h.t.s, h.inst, (int)q, (int)(e - q), (int)p->cp.size()});
+        q = e;
+    }
+    p->ntiles = (int)dtiles.size();
+    // series blocks grouped by (round, n)
+    std::vector<gbs::SeriesBlock> sb;
+    std::map<std::pair<int, int>, std::vector<gbs::SeriesBlock>> by;
+    for (size_t k = 0; k < ht.size(); ++k) {
+        const int n = npair[ht[k].t.item];
+        auto& v = by[{ht[k].round, n}];
+        int64_t pi = tile_pidx[k];
+        for (uint64_t s0 = 0; s0 < ht[k].t.count; s0 += kSeriesBlock)
+            v.push_back(gbs::SeriesBlock{pos_of[k], (int)pi++, s0});
+    }
+    for (auto& kv : by) {
+        p->se.push_back(SeriesLaunch{kv.first.first, kv.first.second, (int)sb.size(), (int)kv.second.size()});
+        sb.insert(sb.end(), kv.second.begin(), kv.second.end());
+    }
+
+    // device buffers
+    gbs_status st;
+    size_t& B = p->bytes;
+    if ((st = dmalloc((void**)&p->staging, sizeof(double2) * (size_t)iin, &B)) != GBS_OK) return st;
+    if ((st = dmalloc((void**)&p->a0, sizeof(double2) * (size_t)ia, &B)) != GBS_OK) return st;
+    if ((st = dmalloc((void**)&p->dv, sizeof(double2) * (size_t)id, &B)) != GBS_OK) return st;
+    std::vector<gbs::BatchItem> hitems(nitems);
+    for (int i = 0; i < nitems; ++i)
+        hitems[i] = gbs::BatchItem{p->a0 + a0_off[i], p->dv + d_off[i], 2 * npair[i], npair[i]};
+    std::vector<int> hdims(dims.begin(), dims.end());
+    if ((st = upload(&p->items, hitems, &B)) != GBS_OK) return st;
+    if ((st = upload(&p->in_off, in_off, &B)) != GBS_OK) return st;
+    if ((st = upload(&p->dims, hdims, &B)) != GBS_OK) return st;
+    if ((st = upload(&p->tiles, dtiles, &B)) != GBS_OK) return st;
+    if ((st = upload(&p->sblocks, sb, &B)) != GBS_OK) return st;
+    if ((st = upload(&p->pbeg, pbeg, &B)) != GBS_OK) return st;
+    if ((st = dmalloc((void**)&p->partials, sizeof(double) * 5 * (size_t)std::max<int64_t>(1, pbeg[nitems]), &B)) !=
+        GBS_OK)
+        return st;
+    if ((st = dmalloc((void**)&p->counters, sizeof(unsigned) * std::max<size_t>(1, p->cp.size()), &B)) != GBS_OK)
+        return st;
+    for (int b = 0; b < 2 && b < p->rounds; ++b)
+        if ((st = dmalloc(&p->ebuf[b], (size_t)ebuf_bytes, &B)) != GBS_OK) return st;
+    if ((st = dmalloc((void**)&p->out, sizeof(double2) * nitems, &B)) != GBS_OK) return st;
+    if ((st = dmalloc((void**)&p->abs, sizeof(double) * nitems, &B)) != GBS_OK) return st;
+
+    // graph capture
+    HIP_TRY(hipStreamCreateWithFlags(&p->cs, hipStreamNonBlocking));
+    for (hipStream_t& s : p->br) HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreate(&p->t0));
+    HIP_TRY(hipEventCreate(&p->t1));
+    auto new_event = [&](hipEvent_t* e) -> hipError_t {
+        hipError_t r = hipEventCreateWithFlags(e, hipEventDisableTiming);
+        if (r == hipSuccess) p->events.push_back(*e);
+        return r;
+    };
+    HIP_TRY(hipStreamBeginCapture(p->cs, hipStreamCaptureModeThreadLocal));
+    HIP_TRY(gbs::launch_fill_u32(p->counters, (int)std::max<size_t>(1, p->cp.size()), p->cs));
+    HIP_TRY(gbs::launch_batch_prep(p->staging, p->in_off, p->dims, p->items, nitems, p->cs));
+    hipEvent_t ev_prep;
+    HIP_TRY(new_event(&ev_prep));
+    HIP_TRY(hipEventRecord(ev_prep, p->cs));
+    std::vector<hipEvent_t> ev_series(p->rounds, nullptr);
+    size_t ci = 0, si = 0;
+    for (int r = 0; r < p->rounds; ++r) {
+        void* E = p->ebuf[r % 2];
+        std::vector<hipEvent_t> joins;
+        int b = 0;
+        for (; ci < p->cp.size() && p->cp[ci].round == r; ++ci, ++b) {
+            const CharpolyLaunch& L = p->cp[ci];
+            hipStream_t bs = p->br[b % kBranches];
+            HIP_TRY(hipStreamWaitEvent(bs, ev_prep, 0));
+            if (r >= 2) HIP_TRY(hipStreamWaitEvent(bs, ev_series[r - 2], 0));
+            const int grid = std::min(L.ntiles, kPersistentWaves);
+            HIP_TRY(gbs::launch_charpoly_batch(L.layout, L.s_rep, p->max_n + 1, fp32 ? 1 : 0, p->tiles + L.tile_begin,
+                                               L.ntiles, p->items, c->binom, p->counters + L.counter, E, grid, bs));
+            hipEvent_t ej;
+            HIP_TRY(new_event(&ej));
+            HIP_TRY(hipEventRecord(ej, bs));
+            joins.push_back(ej);
+        }
+        for (hipEvent_t ej : joins) HIP_TRY(hipStreamWaitEvent(p->cs, ej, 0));
+        for (; si < p->se.size() && p->se[si].round == r; ++si) {
+            const SeriesLaunch& S = p->se[si];
+            HIP_TRY(gbs::launch_series_batch(S.n, fp32 ? 1 : 0, p->sblocks + S.block_begin, S.nblocks, p->tiles,
+                                             p->items, E, kSeriesPerThread, p->partials, p->cs));
+        }
+        HIP_TRY(new_event(&ev_series[r]));
+        HIP_TRY(hipEventRecord(ev_series[r], p->cs));
+    }
+    HIP_TRY(gbs::launch_item_reduce(p->pbeg, nitems, p->partials, p->out, p->abs, p->cs));
+    HIP_TRY(hipStreamEndCapture(p->cs, &p->graph));
+    HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    return GBS_OK;
+}
+
+gbs_status plan_build(DevCtx* c, const std::vector<int>& dims, bool fp32, int64_t tile_subsets, int64_t round_bytes,
+                      gbs_plan** out) {
+    gbs_plan* p = new gbs_plan();
+    const gbs_status st = plan_build_into(c, dims, fp32, tile_subsets, round_bytes, p);
+    if (st != GBS_OK) {
+        // a failed capture leaves the stream capturing: end it and drop the partial graph
+        hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+        if (p->cs && hipStreamIsCapturing(p->cs, &cst) == hipSuccess && cst != hipStreamCaptureStatusNone) {
+            hipGraph_t g = nullptr;
+            hipStreamEndCapture(p->cs, &g);
+            if (g) hipGraphDestroy(g);
+        }
+        plan_free(p);
+        return st;
+    }
+    *out = p;
+    return GBS_OK;
+}
+
+int kernel_nodes_of(const gbs_plan* p) { return 3 + (int)p->cp.size() + (int)p->se.size(); }
+
+gbs_status plan_run(gbs_plan* p, const gbs_z* mats_dev, gbs_z* out_dev, double* abs_dev, hipStream_t s) {
+    if (p->in_elems > 0)
+        HIP_TRY(hipMemcpyAsync(p->staging, mats_dev, sizeof(double2) * (size_t)p->in_elems, hipMemcpyDeviceToDevice,
+                               s));
+    HIP_TRY(hipGraphLaunch(p->exec, s));
+    if (out_dev) HIP_TRY(hipMemcpyAsync(out_dev, p->out, sizeof(double2) * p->count, hipMemcpyDeviceToDevice, s));
+    if (abs_dev) HIP_TRY(hipMemcpyAsync(abs_dev, p->abs, sizeof(double) * p->count, hipMemcpyDeviceToDevice, s));
+    return GBS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gbs_status gbs_batch_plan_create(const int32_t* dims, int32_t count, gbs_precision prec, int32_t flags,
+                                 gbs_plan** plan) {
+    if (!plan || count < 0 || (count > 0 && !dims)) return fail(GBS_E_ARG, "bad batch arguments");
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    std::vector<int> dv(count);
+    for (int i = 0; i < count; ++i) {
+        if (dims[i] < 0) return fail(GBS_E_ARG, "negative dimension at item %d", i);
+        if (dims[i] > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d at item %d exceeds %d", dims[i], i,
+                                               GBS_MAX_DIM);
+        dv[i] = dims[i];
+    }
+    std::lock_guard<std::mutex> lock(g_mutex);
+    DevCtx* c = nullptr;
+    gbs_status st = current_ctx(&c);
+    if (st != GBS_OK) return st;
+    std::vector<bool> seen(gbs::kMaxPairs + 1, false);
+    for (int N : dv) {
+        const int n = (N + 1) / 2;
+        if (n >= 1 && !seen[n]) {
+            seen[n] = true;
+            st = (flags & GBS_PLAN_AUTOTUNE) ? autotune_impl(c, n, nullptr) : maybe_tune(c, n);
+            if (st != GBS_OK) return st;
+        }
+    }
+    int64_t round_bytes = (int64_t)4 << 30;  // per coefficient buffer
+    if (const char* e = std::getenv("GBS_BATCH_ROUND_MB")) round_bytes = std::max<int64_t>(1, atoll(e)) << 20;
+    if (!(flags & GBS_PLAN_AUTOTUNE)) {
+        gbs_plan* p = nullptr;
+        st = plan_build(c, dv, prec == GBS_FP32_COMP, 4096, round_bytes, &p);
+        if (st != GBS_OK) return st;
+        *plan = p;
+        return GBS_OK;
+    }
+    // autotune the tile size on a synthetic batch of the same shape
+    int64_t in_elems = 0;
+    for (int N : dv) in_elems += (int64_t)N * N;
+    std::vector<gbs_z> hin((size_t)std::max<int64_t>(1, in_elems));
+    {
+        uint64_t x = 0x2545F4914F6CDD1Dull;
+        int64_t o = 0;
+        for (int N : dv) {
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j <= i; ++j) {
+                    x ^= x << 13;
+                    x ^= x >> 7;
+                    x ^= x << 17;
+                    const double re = (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+                    const double im = (double)((x * 0x9E3779B97F4A7C15ull) >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+                    hin[o + (int64_t)i * N + j] = hin[o + (int64_t)j * N + i] = gbs_z{0.3 * re, 0.3 * im};
+                }
+            o += (int64_t)N * N;
+        }
+    }
+    gbs_z* din = nullptr;
+    HIP_TRY(hipMalloc((void**)&din, sizeof(gbs_z) * hin.size()));
+    HIP_TRY(hipMemcpy(din, hin.data(), sizeof(gbs_z) * hin.size(), hipMemcpyHostToDevice));
+    gbs_plan* best = nullptr;
+    float best_ms = 1e30f;
+    for (int64_t ts : {1024, 4096, 16384, 65536}) {
+        gbs_plan* p = nullptr;
+        st = plan_build(c, dv, prec == GBS_FP32_COMP, ts, round_bytes, &p);
+        if (st != GBS_OK) break;
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2 && st == GBS_OK; ++rep) {
+            st = plan_run(p, din, nullptr, nullptr, p->cs);
+            if (st != GBS_OK) break;
+            if (hipEventRecord(p->t0, p->cs) != hipSuccess) st = fail(GBS_E_DEVICE, "event record failed");
+            if (st == GBS_OK) st = plan_run(p, din, nullptr, nullptr, p->cs);
+            if (st == GBS_OK && hipEventRecord(p->t1, p->cs) != hipSuccess) st = fail(GBS_E_DEVICE, "event failed");
+            if (st == GBS_OK && hipEventSynchronize(p->t1) != hipSuccess) st = fail(GBS_E_DEVICE, "sync failed");
+            float m = 0.f;
+            if (st == GBS_OK) hipEventElapsedTime(&m, p->t0, p->t1);
+            ms = std::min(ms, m);
+        }
+        if (st != GBS_OK) {
+            plan_free(p);
+            break;
+        }
+        if (ms < best_ms) {
+            if (best) plan_free(best);
+            best = p;
+            best_ms = ms;
+        } else {
+            plan_free(p);
+        }
+    }
+    hipFree(din);
+    if (st != GBS_OK) {
+        if (best) plan_free(best);
+        return st;
+    }
+    best->tune_ms = best_ms;
+    *plan = best;
+    return GBS_OK;
+}
+
+gbs_status gbs_batch_plan_info(const gbs_plan* plan, gbs_batch_info* info) {
+    if (!plan || !info) return fail(GBS_E_ARG, "null plan or info");
+    info->items = plan->count;
+    info->tiles = plan->ntiles;
+    info->rounds = plan->rounds;
+    info->kernel_nodes = kernel_nodes_of(plan);
+    info->subset_terms = plan->subset_terms;
+    info->tile_subsets = plan->tile_subsets;
+    info->workspace_bytes = (int64_t)plan->bytes;
+    info->yardstick_flops = plan->flops;
+    info->tune_ms = plan->tune_ms;
+    return GBS_OK;
+}
+
+gbs_status gbs_batch_run(gbs_plan* plan, const gbs_z* mats_dev, gbs_z* out_dev, double* abs_sum_dev, void* stream) {
+    if (!plan || (!mats_dev && plan->in_elems > 0) || (!out_dev && plan->count > 0))
+        return fail(GBS_E_ARG, "bad batch run arguments");
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (hipSetDevice(plan->device) != hipSuccess) return fail(GBS_E_DEVICE, "hipSetDevice failed");
+    return plan_run(plan, mats_dev, out_dev, abs_sum_dev, reinterpret_cast<hipStream_t>(stream));
+}
+
+void gbs_batch_plan_destroy(gbs_plan* plan) {
+    if (!plan) return;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    hipSetDevice(plan->device);
+    hipDeviceSynchronize();
+    plan_free(plan);
+}
+
+}  // extern "C"

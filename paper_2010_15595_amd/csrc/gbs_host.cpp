@@ -18,12 +18,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/gbs_lhaf.h"
-#include "lhaf_kernels.h"
+#include "gbs_internal.h"
 
 using cplx = std::complex<double>;
 
-namespace {
+namespace gbs_host {
 
 thread_local std::string g_last_error;
 
@@ -37,14 +36,6 @@ gbs_status fail(gbs_status st, const char* fmt, ...) {
     return st;
 }
 
-#define HIP_TRY(call)                                                                            \
-    do {                                                                                         \
-        hipError_t e_ = (call);                                                                  \
-        if (e_ != hipSuccess)                                                                    \
-            return fail(e_ == hipErrorOutOfMemory ? GBS_E_NOMEM : GBS_E_DEVICE, "%s: %s (%s:%d)", \
-                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                       \
-    } while (0)
-
 constexpr uint64_t kChunk = 1ull << 18;  // subsets per phase-1 launch
 constexpr int kPerThread = 8;            // subsets per lane in phase 2
 
@@ -54,39 +45,6 @@ uint64_t binom_host(int a, int b) {
     for (int i = 1; i <= b; ++i) r = r * (uint64_t)(a - b + i) / (uint64_t)i;
     return r;
 }
-
-// Per-device workspace.  All library calls take g_mutex, so one context is
-// used by one call at a time; `done` orders reuse across caller streams.
-struct DevCtx {
-    int device = -1;
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr, t0 = nullptr, t1 = nullptr;
-    uint64_t* binom = nullptr;
-    double2* A0 = nullptr;      // 64 x 64
-    double2* dvec = nullptr;    // 64
-    double2* Ain = nullptr;     // host-call staging, 64 x 64
-    double2* res = nullptr;     // [0] lhaf, [1] (abs_sum, -)
-    double2* E = nullptr;
-    size_t E_cap = 0;           // double2 elements
-    double* partials = nullptr;
-    size_t partials_cap = 0;    // partial records
-    uint64_t* masks = nullptr;
-    double2* terms = nullptr;
-    size_t masks_cap = 0;
-    // lane grid per (n, s); -1 = heuristic default
-    int layout[gbs::kMaxPairs + 1][gbs::kMaxPairs + 1];
-    bool tuned[gbs::kMaxPairs + 1];
-    char name[64] = {0};
-    DevCtx() {
-        for (auto& row : layout)
-            for (int& v : row) v = -1;
-        for (bool& t : tuned) t = false;
-    }
-};
-
-// Consults the autotune cache / runs the tuner once per n (uses the workspace,
-// so it is called before the caller's matrix is prepared).
-gbs_status maybe_tune(DevCtx* c, int n);
 
 int layout_for(const DevCtx* c, int n, int s) {
     const int v = c->layout[n][s];
@@ -271,7 +229,8 @@ gbs_status expand_impl(const gbs_z* B, int32_t M, int64_t ldb, const gbs_z* gamm
 }
 
 // Subset-sum schedule on prepared workspace (ctx->A0, ctx->dvec).
-gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* abs_dev, int* launches) {
+gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* abs_dev, int* launches,
+                   bool fp32) {
     const int n = Np / 2;
     int nl = 0;
     if (n == 0) {
@@ -290,7 +249,8 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
             total_blocks += (len + per_block - 1) / per_block;
         }
     }
-    gbs_status s1 = ensure_buffer((void**)&c->E, &c->E_cap, (size_t)max_len * 2 * (D + 1), sizeof(double2));
+    const size_t vbytes = fp32 ? sizeof(float2) : sizeof(double2);
+    gbs_status s1 = ensure_buffer(&c->E, &c->E_cap, (size_t)max_len * 2 * (D + 1) * vbytes, 1);
     if (s1 != GBS_OK) return s1;
     s1 = ensure_buffer((void**)&c->partials, &c->partials_cap, (size_t)total_blocks * 5, sizeof(double));
     if (s1 != GBS_OK) return s1;
@@ -300,11 +260,11 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
         const double sign = ((n - s) & 1) ? -1.0 : 1.0;
         for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
             const uint64_t len = std::min(kChunk, cnt - st0);
-            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, c->E};
+            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, c->E, fp32 ? 1 : 0};
             const int lay = layout_for(c, n, s);
             HIP_TRY(timed_launch(kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
                                  [&] { return gbs::launch_charpoly(p1, lay, st); }));
-            gbs::LaunchPhase2 p2{c->E, len, D, sign, kPerThread, c->partials + 5 * poff, nullptr};
+            gbs::LaunchPhase2 p2{c->E, fp32 ? 1 : 0, len, D, sign, kPerThread, c->partials + 5 * poff, nullptr};
             HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, st, [&] { return gbs::launch_series(n, p2, st); }));
             poff += (len + per_block - 1) / per_block;
             nl += 2;
@@ -318,7 +278,7 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
 }
 
 // Full evaluation of an expanded host matrix (N x N, diagonal = loop weights).
-gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* diag) {
+gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* diag, bool fp32) {
     DevCtx* c = nullptr;
     gbs_status st = current_ctx(&c);
     if (st != GBS_OK) return st;
@@ -330,7 +290,7 @@ gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* dia
     HIP_TRY(hipEventRecord(c->t0, c->stream));
     if (Np > 0) HIP_TRY(gbs::launch_prep(c->Ain, N, N, Np, c->A0, c->dvec, c->stream));
     int launches = 0;
-    st = run_sum(c, Np, c->stream, c->res, reinterpret_cast<double*>(c->res + 1), &launches);
+    st = run_sum(c, Np, c->stream, c->res, reinterpret_cast<double*>(c->res + 1), &launches, fp32);
     if (st != GBS_OK) return st;
     HIP_TRY(hipEventRecord(c->t1, c->stream));
     double2 h[2];
@@ -371,7 +331,9 @@ bool cholesky(std::vector<cplx>& L, int n) {
     return true;
 }
 
-}  // namespace
+}  // namespace gbs_host
+
+using namespace gbs_host;
 
 extern "C" {
 
@@ -512,19 +474,17 @@ gbs_status gbs_lhaf(const gbs_z* A, int32_t M, int64_t lda, const gbs_z* gamma, 
                     gbs_precision prec, gbs_z* out, gbs_diag* diag) {
     if (!out) return fail(GBS_E_ARG, "null output");
     if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
-    if (prec != GBS_FP64) return fail(GBS_E_UNSUPPORTED, "only GBS_FP64 is implemented");
     std::vector<gbs_z> Aexp;
     int32_t N = 0;
     gbs_status st = expand_impl(A, M, lda, gamma, mult, Aexp, &N);
     if (st != GBS_OK) return st;
     std::lock_guard<std::mutex> lock(g_mutex);
-    return lhaf_host_matrix(Aexp.data(), N, out, diag);
+    return lhaf_host_matrix(Aexp.data(), N, out, diag, prec == GBS_FP32_COMP);
 }
 
 gbs_status gbs_haf(const gbs_z* A, int32_t N, int64_t lda, gbs_precision prec, gbs_z* out, gbs_diag* diag) {
     if (!out) return fail(GBS_E_ARG, "null output");
     if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
-    if (prec != GBS_FP64) return fail(GBS_E_UNSUPPORTED, "only GBS_FP64 is implemented");
     gbs_status st = check_matrix(A, N, lda, "A", true);
     if (st != GBS_OK) return st;
     if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d exceeds %d", N, GBS_MAX_DIM);
@@ -538,14 +498,13 @@ gbs_status gbs_haf(const gbs_z* A, int32_t N, int64_t lda, gbs_precision prec, g
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j) A0[(size_t)i * N + j] = (i == j) ? gbs_z{0.0, 0.0} : A[(int64_t)i * lda + j];
     std::lock_guard<std::mutex> lock(g_mutex);
-    return lhaf_host_matrix(A0.data(), N, out, diag);
+    return lhaf_host_matrix(A0.data(), N, out, diag, prec == GBS_FP32_COMP);
 }
 
 gbs_status gbs_probability(const gbs_z* Q, const gbs_z* alpha, const int32_t* pattern, int32_t M,
                            gbs_precision prec, double* p_out, gbs_z* lhaf_out, gbs_diag* diag) {
     if (!p_out || (M > 0 && !pattern)) return fail(GBS_E_ARG, "null output or pattern");
     if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
-    if (prec != GBS_FP64) return fail(GBS_E_UNSUPPORTED, "only GBS_FP64 is implemented");
     std::vector<gbs_z> B((size_t)M * M), gamma(M);
     double pvac = 0.0;
     gbs_status st = gbs_pure_state(Q, alpha, M, B.data(), gamma.data(), &pvac);
@@ -557,7 +516,7 @@ gbs_status gbs_probability(const gbs_z* Q, const gbs_z* alpha, const int32_t* pa
     gbs_z lh{1.0, 0.0};
     {
         std::lock_guard<std::mutex> lock(g_mutex);
-        st = lhaf_host_matrix(Aexp.data(), N, &lh, diag);
+        st = lhaf_host_matrix(Aexp.data(), N, &lh, diag, prec == GBS_FP32_COMP);
     }
     if (st != GBS_OK) return st;
     double lfact = 0.0;
@@ -571,12 +530,12 @@ gbs_status gbs_lhaf_terms(const gbs_z* A, int32_t N, int64_t lda, const uint64_t
                           gbs_precision prec, gbs_z* terms_out) {
     if (count < 0 || (count > 0 && (!masks || !terms_out))) return fail(GBS_E_ARG, "bad mask list");
     if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
-    if (prec != GBS_FP64) return fail(GBS_E_UNSUPPORTED, "only GBS_FP64 is implemented");
     gbs_status st = check_matrix(A, N, lda, "A", true);
     if (st != GBS_OK) return st;
     if (N < 1) return fail(GBS_E_ARG, "terms need N >= 1");
     if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d exceeds %d", N, GBS_MAX_DIM);
     const int Np = N + (N & 1), n = Np / 2;
+    const bool fp32 = prec == GBS_FP32_COMP;
     for (int64_t j = 0; j < count; ++j)
         if (n < 64 && (masks[j] >> n) != 0) return fail(GBS_E_ARG, "mask %lld has bits beyond n = %d", (long long)j, n);
     std::lock_guard<std::mutex> lock(g_mutex);
@@ -612,15 +571,16 @@ gbs_status gbs_lhaf_terms(const gbs_z* A, int32_t N, int64_t lda, const uint64_t
             if (c->terms) hipFree(c->terms);
             c->terms = nullptr;
             HIP_TRY(hipMalloc((void**)&c->terms, sizeof(double2) * len));
-            st = ensure_buffer((void**)&c->E, &c->E_cap, len * 2 * (D + 1), sizeof(double2));
+            st = ensure_buffer(&c->E, &c->E_cap, len * 2 * (D + 1) * (fp32 ? sizeof(float2) : sizeof(double2)), 1);
             if (st != GBS_OK) return st;
             const size_t nblk = (len + 64 * kPerThread - 1) / (64 * kPerThread);
             st = ensure_buffer((void**)&c->partials, &c->partials_cap, nblk * 5, sizeof(double));
             if (st != GBS_OK) return st;
             HIP_TRY(hipMemcpyAsync(c->masks, grp.data() + off, sizeof(uint64_t) * len, hipMemcpyHostToDevice, c->stream));
-            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, c->E};
+            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, c->E, fp32 ? 1 : 0};
             HIP_TRY(gbs::launch_charpoly(p1, layout_for(c, n, s), c->stream));
-            gbs::LaunchPhase2 p2{c->E, len, D, ((n - s) & 1) ? -1.0 : 1.0, kPerThread, c->partials, c->terms};
+            gbs::LaunchPhase2 p2{c->E, fp32 ? 1 : 0, len, D, ((n - s) & 1) ? -1.0 : 1.0, kPerThread, c->partials,
+                                 c->terms};
             HIP_TRY(gbs::launch_series(n, p2, c->stream));
             std::vector<double2> th(len);
             HIP_TRY(hipMemcpyAsync(th.data(), c->terms, sizeof(double2) * len, hipMemcpyDeviceToHost, c->stream));
@@ -638,7 +598,6 @@ gbs_status gbs_lhaf_device(const gbs_z* A_dev, int32_t N, gbs_precision prec, gb
     if (N < 0 || (N > 0 && !A_dev) || !out_dev) return fail(GBS_E_ARG, "bad device arguments");
     if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d exceeds %d", N, GBS_MAX_DIM);
     if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
-    if (prec != GBS_FP64) return fail(GBS_E_UNSUPPORTED, "only GBS_FP64 is implemented");
     std::lock_guard<std::mutex> lock(g_mutex);
     DevCtx* c = nullptr;
     gbs_status st = current_ctx(&c);
@@ -650,7 +609,7 @@ gbs_status gbs_lhaf_device(const gbs_z* A_dev, int32_t N, gbs_precision prec, gb
     HIP_TRY(hipStreamWaitEvent(s, c->done, 0));
     if (Np > 0)
         HIP_TRY(gbs::launch_prep(reinterpret_cast<const double2*>(A_dev), N, N, Np, c->A0, c->dvec, s));
-    st = run_sum(c, Np, s, reinterpret_cast<double2*>(out_dev), abs_sum_dev, nullptr);
+    st = run_sum(c, Np, s, reinterpret_cast<double2*>(out_dev), abs_sum_dev, nullptr, prec == GBS_FP32_COMP);
     if (st != GBS_OK) return st;
     HIP_TRY(hipEventRecord(c->done, s));
     return GBS_OK;
@@ -719,7 +678,9 @@ gbs_status gbs_set_layout(int32_t n, int32_t s, int32_t layout) {
     return GBS_OK;
 }
 
-namespace {
+}  // extern "C"
+
+namespace gbs_host {
 
 // Reads "<arch> <n> <s> <layout>" lines of the autotune cache for this device.
 bool cache_load(DevCtx* c, int n) {
@@ -773,7 +734,7 @@ gbs_status autotune_impl(DevCtx* c, int n, gbs_tune_report* rep) {
     const uint64_t sample_cap = 1ull << 16;
     uint64_t max_len = 0;
     for (int s = 1; s <= n; ++s) max_len = std::max(max_len, std::min(sample_cap, binom_host(n, s)));
-    gbs_status st = ensure_buffer((void**)&c->E, &c->E_cap, (size_t)max_len * 2 * (D + 1), sizeof(double2));
+    gbs_status st = ensure_buffer(&c->E, &c->E_cap, (size_t)max_len * 2 * (D + 1) * sizeof(double2), 1);
     if (st != GBS_OK) return st;
     if (rep) {
         std::memset(rep, 0, sizeof *rep);
@@ -785,7 +746,7 @@ gbs_status autotune_impl(DevCtx* c, int n, gbs_tune_report* rep) {
         int best_lay = gbs::charpoly_default_layout(2 * s);
         for (int lay = 0; lay < gbs::kNumLayouts; ++lay) {
             if (!gbs::charpoly_layout_ok(2 * s, lay)) continue;
-            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, nullptr, c->binom, D, c->E};
+            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, nullptr, c->binom, D, c->E, 0};
             HIP_TRY(gbs::launch_charpoly(p1, lay, c->stream));  // warm-up
             HIP_TRY(hipEventRecord(c->t0, c->stream));
             const int reps = 3;
@@ -819,7 +780,9 @@ gbs_status maybe_tune(DevCtx* c, int n) {
     return GBS_OK;
 }
 
-}  // namespace
+}  // namespace gbs_host
+
+extern "C" {
 
 gbs_status gbs_autotune(int32_t n, gbs_tune_report* report) {
     if (n < 1 || n > gbs::kMaxPairs) return fail(GBS_E_ARG, "n = %d out of range", n);

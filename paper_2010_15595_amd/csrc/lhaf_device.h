@@ -335,17 +335,51 @@ __device__ __forceinline__ void householder(double norm2, double2 x0, double& sc
     }
 }
 
+// ---- La Budde number type: double2 (FP64 path) or float2 (FP32 path) ----
+
+template <class V> struct CxT;
+template <> struct CxT<double2> { using S = double; };
+template <> struct CxT<float2> { using S = float; };
+
+template <class V> __device__ __forceinline__ V vmk(typename CxT<V>::S x, typename CxT<V>::S y) {
+    V r;
+    r.x = x;
+    r.y = y;
+    return r;
+}
+template <class V> __device__ __forceinline__ V vzero() { return vmk<V>(0, 0); }
+template <class V> __device__ __forceinline__ V vone() { return vmk<V>(1, 0); }
+template <class V> __device__ __forceinline__ V vconv(double2 z) {
+    return vmk<V>((typename CxT<V>::S)z.x, (typename CxT<V>::S)z.y);
+}
+template <class V> __device__ __forceinline__ V vmul(V a, V b) {
+    return vmk<V>(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// c - a * b
+template <class V> __device__ __forceinline__ V vfms(V a, V b, V c) {
+    return vmk<V>(fma(-a.x, b.x, fma(a.y, b.y, c.x)), fma(-a.x, b.y, fma(-a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double shr1(double x) { return dpp_mov<0x138>(x); }  // wave_shr:1
+__device__ __forceinline__ float shr1(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float swap_sum32(float x) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 struct Lds {
     double2* vbuf;   // [W][64]: source column of the current reflector
     double2* misc;   // [W][2]: squared norm, alpha (border subdiagonal)
     int* idx;        // [W][64]: vertex indices of the subset
     double2* rowbuf; // [NT][64]: current row of H' (La Budde)
-    double2* betab;  // [NT][64]: beta_k of the current row
-    double2* ring;   // [NT][RS * RS]: last RS trailing characteristic polynomials
+    void* betab;     // [NT][64]: beta_k of the current row (La Budde type)
+    void* ring;      // [NT][RS * RS]: last RS trailing characteristic polynomials
 };
 
-__host__ __device__ constexpr int lds_doubles2(int W, int NT, int D) {
-    return W * (64 + 2 + 16) + NT * (128 + (D + 1) * (D + 1));
+// LDS bytes of the per-subset kernel; vbytes = size of the La Budde complex type.
+__host__ __device__ constexpr size_t charpoly_lds_bytes(int W, int NT, int D, int vbytes) {
+    return (size_t)16 * (W * (64 + 2 + 16) + NT * 64) + (size_t)vbytes * NT * (64 + (D + 1) * (D + 1));
 }
 
 template <int P, int Q, int MR, int MC, int KJ>
@@ -424,45 +458,46 @@ __device__ __forceinline__ void hess_all(double2 (&a)[MR][MC], double2 (&y)[MC],
 // With split = 2 (64-lane team, D + 1 <= 32) the lanes d and d + 32 share
 // coefficient d: the low half takes odd k, the high half even k, and the two
 // partial sums are added across the halves.
-__device__ __forceinline__ void labudde_step(int rho, int m, int D, int d, int half, int split, double2 hrr,
-                                             double2 sub_in, double2& pik, const double2* __restrict__ rowbuf,
-                                             double2* __restrict__ betab, double2* __restrict__ ring) {
+template <class V>
+__device__ __forceinline__ void labudde_step(int rho, int m, int D, int d, int half, int split, V hrr, V sub_in,
+                                             V& pik, const double2* __restrict__ rowbuf, V* __restrict__ betab,
+                                             V* __restrict__ ring) {
     const int RS = D + 1;
     const int r = rho + 1;
     // pi_{r,k} = H'[r+1][r] pi_{r+1,k-1} (lane shift by one), pi_{r,0} = 1
-    const double2 sh = make_double2(dpp_mov<0x138>(pik.x), dpp_mov<0x138>(pik.y));  // wave_shr:1
-    pik = (d == 0) ? make_double2(1.0, 0.0) : cmul(sub_in, sh);
+    const V sh = vmk<V>(shr1(pik.x), shr1(pik.y));
+    pik = (d == 0) ? vone<V>() : vmul(sub_in, sh);
     const int K = min(D - 1, m - rho - 1);
-    if (half == 0 && d >= 1 && d <= K) betab[d] = cmul(rowbuf[rho + d], pik);
+    if (half == 0 && d >= 1 && d <= K) betab[d] = vmul(vconv<V>(rowbuf[rho + d]), pik);
     wave_sync();
-    double2 e = cz();
+    V e = vzero<V>();
     if (d <= D) {
-        const double2* prev = ring + ((r + 1) % RS) * RS;
+        const V* prev = ring + ((r + 1) % RS) * RS;
         if (half == 0) {
             e = prev[d];
-            if (d >= 1) e = cfms(hrr, prev[d - 1], e);
+            if (d >= 1) e = vfms(hrr, prev[d - 1], e);
         }
         const int kmax = min(K, d - 1);
         // element of poly r+k+1 at coefficient d-k-1: ring[slot(k) * RS + d - k - 1]
         int slot = (r + 2 + half) % RS;
-        const double2* base = ring + d - 1;
+        const V* base = ring + d - 1;
         for (int k = 1 + half; k <= kmax; k += split) {
-            e = cfms(betab[k], base[slot * RS - k], e);
+            e = vfms(betab[k], base[slot * RS - k], e);
             slot += split;
             if (slot >= RS) slot -= RS;
         }
     }
-    if (split == 2) e = make_double2(swap_sum32(e.x), swap_sum32(e.y));
+    if (split == 2) e = vmk<V>(swap_sum32(e.x), swap_sum32(e.y));
     if (half == 0 && d <= D) ring[(r % RS) * RS + d] = e;
     wave_sync();
 }
 
-template <int P, int Q, int MR, int MC, int I>
+template <int P, int Q, int MR, int MC, int I, class V>
 __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, int D, int d, int half, int split,
                                              int pr, int pc,
                                              bool row_owner_group, double2* __restrict__ rowbuf_own,
-                                             const double2* __restrict__ rowbuf, double2* __restrict__ betab,
-                                             double2* __restrict__ ring, double2& pik, double2& sub) {
+                                             const double2* __restrict__ rowbuf, V* __restrict__ betab,
+                                             V* __restrict__ ring, V& pik, V& sub) {
     if constexpr (I >= 0) {
         for (int p = P - 1; p >= 0; --p) {
             const int rho = p + P * I;
@@ -472,25 +507,28 @@ __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, 
                 for (int k = 0; k < MC; ++k) rowbuf_own[pc + Q * k] = a[I][k];
             }
             wave_sync();
-            const double2 hrr = rowbuf[rho];
-            const double2 sub_next = (rho >= 1) ? rowbuf[rho - 1] : cz();
-            labudde_step(rho, m, D, d, half, split, hrr, sub, pik, rowbuf, betab, ring);
+            const V hrr = vconv<V>(rowbuf[rho]);
+            const V sub_next = (rho >= 1) ? vconv<V>(rowbuf[rho - 1]) : vzero<V>();
+            labudde_step<V>(rho, m, D, d, half, split, hrr, sub, pik, rowbuf, betab, ring);
             sub = sub_next;
         }
-        labudde_rows<P, Q, MR, MC, I - 1>(a, m, D, d, half, split, pr, pc, row_owner_group, rowbuf_own, rowbuf,
-                                          betab, ring, pik, sub);
+        labudde_rows<P, Q, MR, MC, I - 1, V>(a, m, D, d, half, split, pr, pc, row_owner_group, rowbuf_own, rowbuf,
+                                             betab, ring, pik, sub);
     }
 }
 
-template <int P, int Q, int MR, int MC>
-__global__ void __launch_bounds__(64) charpoly_kernel(const double2* __restrict__ A0, const double2* __restrict__ dvec,
-                                                      int Np, int s, uint64_t rank0, uint64_t count,
-                                                      const uint64_t* __restrict__ masks,
-                                                      const uint64_t* __restrict__ binom, int D, int T,
-                                                      double2* __restrict__ Eout) {
+// One wavefront's work: the W subsets with local indices first .. first+W-1
+// of a run of `count` subsets of size s (colex ranks rank0 + index, or the
+// explicit masks), each written to Eout + index * 2(D+1).
+// V: complex type of the La Budde recurrence and of the output (double2 for
+// the FP64 path, float2 for the FP32 path; the Hessenberg reduction is FP64).
+template <int P, int Q, int MR, int MC, class V>
+__device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, const double2* __restrict__ dvec, int Np,
+                                              int s, uint64_t rank0, uint64_t count, uint64_t first,
+                                              const uint64_t* __restrict__ masks, const uint64_t* __restrict__ binom,
+                                              int D, int T, V* __restrict__ Eout, double2* __restrict__ lds) {
     constexpr int G = P * Q;
     constexpr int W = 64 / G;
-    extern __shared__ double2 lds[];
     const int lane = threadIdx.x;
     const int g = lane / G;
     const int pr = lane % P;
@@ -505,14 +543,13 @@ __global__ void __launch_bounds__(64) charpoly_kernel(const double2* __restrict_
     L.idx = reinterpret_cast<int*>(lds + W * 66);
     L.rowbuf = lds + W * 82;
     L.betab = L.rowbuf + NT * 64;
-    L.ring = L.betab + NT * 64;
+    L.ring = reinterpret_cast<V*>(L.betab) + NT * 64;
     double2* vb = L.vbuf + g * 64;
     double2* nb = L.misc + g * 2;
     int* idx = L.idx + g * 64;
 
     // subsets of this wave (one per group); the mask list or colex unranking
     // is evaluated on the scalar unit for every group, then selected per lane
-    const uint64_t first = (uint64_t)blockIdx.x * W;
     uint64_t mask = 0;
 #pragma unroll
     for (int q = 0; q < W; ++q) {
@@ -615,28 +652,68 @@ __global__ void __launch_bounds__(64) charpoly_kernel(const double2* __restrict_
         const bool own = (g / NT) == pass;        // my group's rows are read this pass
         double2* rowbuf_own = L.rowbuf + (g % NT) * 64;
         double2* rowbuf = L.rowbuf + team * 64;
-        double2* betab = L.betab + team * 64;
-        double2* ring = L.ring + team * RS * RS;
-        if (half == 0 && d < RS) ring[(Mp % RS) * RS + d] = (d == 0) ? make_double2(1.0, 0.0) : cz();
-        double2 pik = (d == 0) ? make_double2(1.0, 0.0) : cz();
-        double2 sub = cz();
+        V* betab = reinterpret_cast<V*>(L.betab) + team * 64;
+        V* ring = reinterpret_cast<V*>(L.ring) + team * RS * RS;
+        if (half == 0 && d < RS) ring[(Mp % RS) * RS + d] = (d == 0) ? vone<V>() : vzero<V>();
+        V pik = (d == 0) ? vone<V>() : vzero<V>();
+        V sub = vzero<V>();
         wave_sync();
-        labudde_rows<P, Q, MR, MC, MR - 1>(a, m, D, d, half, split, pr, pc, own, rowbuf_own, rowbuf, betab, ring,
-                                           pik, sub);
+        labudde_rows<P, Q, MR, MC, MR - 1, V>(a, m, D, d, half, split, pr, pc, own, rowbuf_own, rowbuf, betab, ring,
+                                              pik, sub);
         // border row: H'[0][k] = y''_{k-1}, H'[0][0] = 0, H'[1][0] = alpha
         if (own && pr == 0) {
 #pragma unroll
             for (int k = 0; k < MC; ++k) rowbuf_own[pc + Q * k] = y[k];
         }
         wave_sync();
-        const double2 alpha_t = L.misc[gt * 2 + 1];
-        labudde_step(-1, m, D, d, half, split, cz(), alpha_t, pik, rowbuf, betab, ring);
+        const V alpha_t = vconv<V>(L.misc[gt * 2 + 1]);
+        labudde_step<V>(-1, m, D, d, half, split, vzero<V>(), alpha_t, pik, rowbuf, betab, ring);
         const uint64_t gi = first + gt;
         if (half == 0 && d <= D && gi < count) {
-            double2* out = Eout + gi * (uint64_t)(2 * RS);
+            V* out = Eout + gi * (uint64_t)(2 * RS);
             out[d] = ring[(1 % RS) * RS + d];
             out[RS + d] = ring[d];
         }
+        wave_sync();
+    }
+}
+
+
+template <int P, int Q, int MR, int MC, class V>
+__global__ void __launch_bounds__(64) charpoly_kernel(const double2* __restrict__ A0, const double2* __restrict__ dvec,
+                                                      int Np, int s, uint64_t rank0, uint64_t count,
+                                                      const uint64_t* __restrict__ masks,
+                                                      const uint64_t* __restrict__ binom, int D, int T,
+                                                      V* __restrict__ Eout) {
+    extern __shared__ double2 lds[];
+    constexpr int W = 64 / (P * Q);
+    charpoly_wave<P, Q, MR, MC, V>(A0, dvec, Np, s, rank0, count, (uint64_t)blockIdx.x * W, masks, binom, D, T, Eout,
+                                   lds);
+}
+
+// Persistent form for batches: every wavefront takes tiles from `tiles`
+// (largest first) through a device counter until none is left, and runs all
+// subsets of each tile.  The counter is cleared by the caller's fill kernel.
+template <int P, int Q, int MR, int MC, class V>
+__global__ void __launch_bounds__(64) charpoly_batch_kernel(const BatchTile* __restrict__ tiles, int ntiles,
+                                                            const BatchItem* __restrict__ items,
+                                                            const uint64_t* __restrict__ binom,
+                                                            unsigned* __restrict__ counter, V* __restrict__ Ebase) {
+    extern __shared__ double2 lds[];
+    constexpr int G = P * Q;
+    constexpr int W = 64 / G;
+    for (;;) {
+        int t = 0;
+        if (threadIdx.x == 0) t = (int)atomicAdd(counter, 1u);
+        t = __shfl(t, 0);
+        if (t >= ntiles) break;
+        const BatchTile tl = tiles[t];
+        const BatchItem it = items[tl.item];
+        const int D = it.n + 1;
+        const int T = (G >= D + 1) ? G : 64;
+        for (uint64_t first = 0; first < tl.count; first += W)
+            charpoly_wave<P, Q, MR, MC, V>(it.A0, it.dvec, it.Np, tl.s, tl.rank0, tl.count, first, nullptr, binom, D,
+                                           T, Ebase + tl.eoff, lds);
         wave_sync();
     }
 }

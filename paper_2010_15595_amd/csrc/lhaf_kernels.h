@@ -21,12 +21,14 @@ struct LaunchPhase1 {
     const uint64_t* masks; // explicit subset masks or nullptr
     const uint64_t* binom; // device binomial table
     int D;                 // n + 1
-    double2* Eout;         // count * 2 * (D + 1)
+    void* Eout;            // count * 2 * (D + 1) complex (double2, or float2 when fp32)
+    int fp32;              // La Budde in complex FP32
 };
 
 // Phase 2: one lane per subset; signed terms, compensated block partials.
 struct LaunchPhase2 {
-    const double2* E;
+    const void* E;         // double2, or float2 when fp32
+    int fp32;              // series and per-lane compensated sums in FP32
     uint64_t count;
     int D;
     double sign;        // (-1)^(n - s)
@@ -40,6 +42,43 @@ enum { kLayout44 = 0, kLayout84 = 1, kLayout88 = 2, kNumLayouts = 3 };
 bool charpoly_layout_ok(int m, int layout);
 int charpoly_default_layout(int m);
 hipError_t launch_charpoly(const LaunchPhase1& p, int layout, hipStream_t st);
+
+// ---- batches of loop hafnians ----
+struct BatchItem {
+    const double2* A0;     // Np x Np, zero diagonal
+    const double2* dvec;   // Np
+    int Np, n;
+};
+// A run of `count` subsets of size s of one item, colex ranks rank0.. ;
+// coefficients at Ebase + eoff (elements of the path's complex type).
+struct BatchTile {
+    uint64_t rank0;
+    uint64_t count;
+    uint64_t eoff;
+    int item, s;
+};
+// One series block: up to 64 * per_thread subsets of a tile starting at sub0.
+struct SeriesBlock {
+    int tile;
+    int pidx;
+    uint64_t sub0;
+};
+
+// Persistent per-subset kernel over tiles that all use grid `layout` with the
+// same (MR, MC) as subsets of size s_rep; D_max sizes the LDS.
+hipError_t launch_charpoly_batch(int layout, int s_rep, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+                                 const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
+                                 int grid, hipStream_t st);
+// Kernel instance id (layout, MR, MC) of subsets of size s under `layout`.
+int charpoly_instance(int layout, int s);
+hipError_t launch_series_batch(int n, int fp32, const SeriesBlock* blocks, int nblocks, const BatchTile* tiles,
+                               const BatchItem* items, const void* Ebase, int per_thread, double* partials,
+                               hipStream_t st);
+hipError_t launch_item_reduce(const int64_t* pbeg, int nitems, const double* partials, double2* out, double* abs_out,
+                              hipStream_t st);
+hipError_t launch_batch_prep(const double2* mats, const int64_t* in_off, const int* N, BatchItem* items, int nitems,
+                             hipStream_t st);
+hipError_t launch_fill_u32(unsigned* p, int count, hipStream_t st);
 hipError_t launch_series(int n, const LaunchPhase2& p, hipStream_t st);
 hipError_t launch_final_reduce(const double* partials, int64_t np, double2* out, double* abs_out, hipStream_t st);
 hipError_t launch_prep(const double2* A, int N, int64_t lda, int Np, double2* A0, double2* d, hipStream_t st);

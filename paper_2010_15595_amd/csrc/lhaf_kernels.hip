@@ -84,55 +84,83 @@ __device__ __forceinline__ double shfl_xor_d(double x, int m) {
 //   L = (R - R') / (eta R):  L_k = (R_{k+1} - R'_{k+1}) - sum_{j<k} R_j L_{k-j}
 //   c_k = p_k / (2k) + L_k / 2
 //   e_0 = 1, e_k = (1/k) sum_{j<=k} j c_j e_{k-j};  t = sign * e_n
-template <int NN>
-__device__ __forceinline__ double2 series_term(const double2* __restrict__ E, int RS, double sign) {
-    double2 R[NN + 2], c[NN + 1];
+// V is double2 (FP64 path) or float2 (FP32 path).
+template <int NN, class V>
+__device__ __forceinline__ V series_term(const V* __restrict__ E, int RS, double sign) {
+    using S = typename CxT<V>::S;
+    V R[NN + 2], c[NN + 1];
 #pragma unroll
     for (int k = 0; k <= NN + 1; ++k) R[k] = E[k];
     {
-        double2 Lk[NN + 1], p[NN + 1];
-        Lk[0] = cz();
+        V Lk[NN + 1], p[NN + 1];
+        Lk[0] = vzero<V>();
 #pragma unroll
         for (int k = 1; k <= NN; ++k) {
-            double2 acc = csub(R[k + 1], E[RS + k + 1]);
+            const V rp = E[RS + k + 1];
+            V acc = vmk<V>(R[k + 1].x - rp.x, R[k + 1].y - rp.y);
 #pragma unroll
-            for (int j = 1; j < k; ++j) acc = cfms(R[j], Lk[k - j], acc);
+            for (int j = 1; j < k; ++j) acc = vfms(R[j], Lk[k - j], acc);
             Lk[k] = acc;
-            double2 pk = cscale(R[k], -(double)k);
+            V pk = vmk<V>(-(S)k * R[k].x, -(S)k * R[k].y);
 #pragma unroll
-            for (int j = 1; j < k; ++j) pk = cfms(R[j], p[k - j], pk);
+            for (int j = 1; j < k; ++j) pk = vfms(R[j], p[k - j], pk);
             p[k] = pk;
-            c[k] = cadd(cscale(pk, 0.5 / k), cscale(acc, 0.5));
+            const S hk = (S)0.5 / (S)k;
+            c[k] = vmk<V>(fma(pk.x, hk, (S)0.5 * acc.x), fma(pk.y, hk, (S)0.5 * acc.y));
         }
     }
-    double2 e[NN + 1];
-    e[0] = make_double2(1.0, 0.0);
+    V e[NN + 1];
+    e[0] = vone<V>();
 #pragma unroll
     for (int k = 1; k <= NN; ++k) {
-        double2 acc = cz();
+        V acc = vzero<V>();
 #pragma unroll
-        for (int j = 1; j <= k; ++j) acc = cfma(cscale(c[j], (double)j), e[k - j], acc);
-        e[k] = cscale(acc, 1.0 / k);
+        for (int j = 1; j <= k; ++j) {
+            const V cj = vmk<V>((S)j * c[j].x, (S)j * c[j].y);
+            acc = vfms(vmk<V>(-cj.x, -cj.y), e[k - j], acc);
+        }
+        const S ik = (S)1 / (S)k;
+        e[k] = vmk<V>(acc.x * ik, acc.y * ik);
     }
-    return cscale(e[NN], sign);
+    return vmk<V>(e[NN].x * (S)sign, e[NN].y * (S)sign);
 }
 
-template <int NN>
-__global__ void __launch_bounds__(64) series_kernel(const double2* __restrict__ E, uint64_t count, int D,
-                                                    double sign, int per_thread, double* __restrict__ partials,
+template <class S>
+__device__ __forceinline__ void two_sum_t(S a, S b, S& s, S& e) {
+    s = a + b;
+    const S bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// One lane per subset.  Each lane accumulates its terms with TwoSum in the
+// path's precision (FP32 compensated on the FP32 path); lanes and blocks are
+// combined in FP64 in a fixed order.
+template <int NN, class V>
+__global__ void __launch_bounds__(64) series_kernel(const V* __restrict__ E, uint64_t count, int D, double sign,
+                                                    int per_thread, double* __restrict__ partials,
                                                     double2* __restrict__ terms) {
+    using S = typename CxT<V>::S;
     const int lane = threadIdx.x;
     const int RS = D + 1;
-    Acc A{0.0, 0.0, 0.0, 0.0, 0.0};
+    S sr = 0, cr = 0, si = 0, ci = 0;
+    double ab = 0.0;
     const uint64_t base = (uint64_t)blockIdx.x * 64 * per_thread;
     for (int q = 0; q < per_thread; ++q) {
         const uint64_t g = base + (uint64_t)q * 64 + lane;
         if (g < count) {
-            const double2 t = series_term<NN>(E + g * (uint64_t)(2 * RS), RS, sign);
-            if (terms) terms[g] = t;
-            acc_add(A, t);
+            const V t = series_term<NN, V>(E + g * (uint64_t)(2 * RS), RS, sign);
+            if (terms) terms[g] = make_double2((double)t.x, (double)t.y);
+            S sn, en;
+            two_sum_t<S>(sr, t.x, sn, en);
+            sr = sn;
+            cr += en;
+            two_sum_t<S>(si, t.y, sn, en);
+            si = sn;
+            ci += en;
+            ab += sqrt((double)t.x * t.x + (double)t.y * t.y);
         }
     }
+    Acc A{(double)sr, (double)cr, (double)si, (double)ci, ab};
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         Acc B;
@@ -157,6 +185,118 @@ __global__ void __launch_bounds__(64) series_kernel(const double2* __restrict__ 
         o[3] = A.ci;
         o[4] = A.ab;
     }
+}
+
+// Batched series: block b runs up to 64 * per_thread subsets of one tile
+// (all tiles of the launch have n = NN pairs).
+template <int NN, class V>
+__global__ void __launch_bounds__(64) series_batch_kernel(const SeriesBlock* __restrict__ blocks,
+                                                          const BatchTile* __restrict__ tiles,
+                                                          const V* __restrict__ Ebase, int per_thread,
+                                                          double* __restrict__ partials) {
+    using S = typename CxT<V>::S;
+    const int lane = threadIdx.x;
+    const SeriesBlock b = blocks[blockIdx.x];
+    const BatchTile tl = tiles[b.tile];
+    constexpr int RS = NN + 2;
+    const double sign = ((NN - tl.s) & 1) ? -1.0 : 1.0;
+    S sr = 0, cr = 0, si = 0, ci = 0;
+    double ab = 0.0;
+    for (int q = 0; q < per_thread; ++q) {
+        const uint64_t g = b.sub0 + (uint64_t)q * 64 + lane;
+        if (g < tl.count) {
+            const V t = series_term<NN, V>(Ebase + tl.eoff + g * (uint64_t)(2 * RS), RS, sign);
+            S sn, en;
+            two_sum_t<S>(sr, t.x, sn, en);
+            sr = sn;
+            cr += en;
+            two_sum_t<S>(si, t.y, sn, en);
+            si = sn;
+            ci += en;
+            ab += sqrt((double)t.x * t.x + (double)t.y * t.y);
+        }
+    }
+    Acc A{(double)sr, (double)cr, (double)si, (double)ci, ab};
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        Acc B;
+        B.sr = shfl_xor_d(A.sr, off);
+        B.cr = shfl_xor_d(A.cr, off);
+        B.si = shfl_xor_d(A.si, off);
+        B.ci = shfl_xor_d(A.ci, off);
+        B.ab = shfl_xor_d(A.ab, off);
+        if (lane & off) {
+            Acc T = B;
+            acc_merge(T, A);
+            A = T;
+        } else {
+            acc_merge(A, B);
+        }
+    }
+    if (lane == 0) {
+        double* o = partials + 5 * (uint64_t)b.pidx;
+        o[0] = A.sr;
+        o[1] = A.cr;
+        o[2] = A.si;
+        o[3] = A.ci;
+        o[4] = A.ab;
+    }
+}
+
+// Per-item fixed-order reduction of partials [pbeg[i], pbeg[i+1]).
+__global__ void __launch_bounds__(64) item_reduce_kernel(const int64_t* __restrict__ pbeg,
+                                                         const double* __restrict__ partials,
+                                                         double2* __restrict__ out, double* __restrict__ abs_out) {
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
+    Acc A{0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t k = pbeg[i] + lane; k < pbeg[i + 1]; k += 64) {
+        Acc B{partials[5 * k], partials[5 * k + 1], partials[5 * k + 2], partials[5 * k + 3], partials[5 * k + 4]};
+        acc_merge(A, B);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        Acc B;
+        B.sr = shfl_xor_d(A.sr, off);
+        B.cr = shfl_xor_d(A.cr, off);
+        B.si = shfl_xor_d(A.si, off);
+        B.ci = shfl_xor_d(A.ci, off);
+        B.ab = shfl_xor_d(A.ab, off);
+        if (lane & off) {
+            Acc T = B;
+            acc_merge(T, A);
+            A = T;
+        } else {
+            acc_merge(A, B);
+        }
+    }
+    if (lane == 0) {
+        const bool empty = pbeg[i + 1] == pbeg[i];  // n = 0: lhaf = 1
+        out[i] = empty ? make_double2(1.0, 0.0) : make_double2(A.sr + A.cr, A.si + A.ci);
+        if (abs_out) abs_out[i] = empty ? 1.0 : A.ab;
+    }
+}
+
+// Batch prep: item i (N[i] x N[i] at mats + in_off[i]) -> its A0 and d.
+__global__ void __launch_bounds__(256) batch_prep_kernel(const double2* __restrict__ mats,
+                                                         const int64_t* __restrict__ in_off,
+                                                         const int* __restrict__ Ns,
+                                                         const BatchItem* __restrict__ items) {
+    const int i = blockIdx.x;
+    const BatchItem it = items[i];
+    const int N = Ns[i], Np = it.Np;
+    const double2* A = mats + in_off[i];
+    double2* A0 = const_cast<double2*>(it.A0);
+    double2* d = const_cast<double2*>(it.dvec);
+    for (int e = threadIdx.x; e < Np * Np; e += blockDim.x) {
+        const int r = e / Np, c = e % Np;
+        A0[e] = (r < N && c < N && r != c) ? A[(int64_t)r * N + c] : cz();
+        if (r == c) d[r] = (r < N) ? A[(int64_t)r * N + r] : make_double2(1.0, 0.0);
+    }
+}
+
+__global__ void __launch_bounds__(64) fill_u32_kernel(unsigned* __restrict__ p, int count) {
+    for (int i = threadIdx.x; i < count; i += 64) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------- reductions / prep
@@ -260,6 +400,90 @@ bool charpoly_layout_ok(int m, int layout) {
 
 int charpoly_default_layout(int m) { return m <= 16 ? kLayout44 : (m <= 32 ? kLayout84 : kLayout88); }
 
+hipError_t launch_charpoly_batch_l44(int s_rep, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+                                     const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
+                                     int grid, hipStream_t st);
+hipError_t launch_charpoly_batch_l84(int s_rep, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+                                     const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
+                                     int grid, hipStream_t st);
+hipError_t launch_charpoly_batch_l88(int s_rep, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+                                     const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
+                                     int grid, hipStream_t st);
+
+int charpoly_instance(int layout, int s) {
+    const int m = 2 * s;
+    switch (layout) {
+        case kLayout44: return 100 + (m + 3) / 4;
+        case kLayout84: return 200 + (m + 3) / 4;
+        default: return 300 + (m + 7) / 8;
+    }
+}
+
+hipError_t launch_charpoly_batch(int layout, int s_rep, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+                                 const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
+                                 int grid, hipStream_t st) {
+    if (!charpoly_layout_ok(2 * s_rep, layout)) return hipErrorInvalidValue;
+    switch (layout) {
+        case kLayout44:
+            return launch_charpoly_batch_l44(s_rep, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
+        case kLayout84:
+            return launch_charpoly_batch_l84(s_rep, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
+        default:
+            return launch_charpoly_batch_l88(s_rep, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
+    }
+}
+
+template <int NN>
+static hipError_t launch_series_batch_nn(int fp32, const SeriesBlock* blocks, int nblocks, const BatchTile* tiles,
+                                         const void* Ebase, int per_thread, double* partials, hipStream_t st) {
+    if (fp32)
+        hipLaunchKernelGGL((series_batch_kernel<NN, float2>), dim3(nblocks), dim3(64), 0, st, blocks, tiles,
+                           static_cast<const float2*>(Ebase), per_thread, partials);
+    else
+        hipLaunchKernelGGL((series_batch_kernel<NN, double2>), dim3(nblocks), dim3(64), 0, st, blocks, tiles,
+                           static_cast<const double2*>(Ebase), per_thread, partials);
+    return hipGetLastError();
+}
+
+template <int NN>
+static hipError_t series_batch_dispatch(int n, int fp32, const SeriesBlock* blocks, int nblocks,
+                                        const BatchTile* tiles, const void* Ebase, int per_thread, double* partials,
+                                        hipStream_t st) {
+    if constexpr (NN > kMaxPairs) {
+        return hipErrorInvalidValue;
+    } else {
+        if (n == NN) return launch_series_batch_nn<NN>(fp32, blocks, nblocks, tiles, Ebase, per_thread, partials, st);
+        return series_batch_dispatch<NN + 1>(n, fp32, blocks, nblocks, tiles, Ebase, per_thread, partials, st);
+    }
+}
+
+hipError_t launch_series_batch(int n, int fp32, const SeriesBlock* blocks, int nblocks, const BatchTile* tiles,
+                               const BatchItem* items, const void* Ebase, int per_thread, double* partials,
+                               hipStream_t st) {
+    (void)items;
+    if (nblocks <= 0) return hipSuccess;
+    return series_batch_dispatch<1>(n, fp32, blocks, nblocks, tiles, Ebase, per_thread, partials, st);
+}
+
+hipError_t launch_item_reduce(const int64_t* pbeg, int nitems, const double* partials, double2* out, double* abs_out,
+                              hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(item_reduce_kernel, dim3(nitems), dim3(64), 0, st, pbeg, partials, out, abs_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_prep(const double2* mats, const int64_t* in_off, const int* N, BatchItem* items, int nitems,
+                             hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_prep_kernel, dim3(nitems), dim3(256), 0, st, mats, in_off, N, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned* p, int count, hipStream_t st) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, p, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_charpoly(const LaunchPhase1& p, int layout, hipStream_t st) {
     const int m = 2 * p.s;
     if (!charpoly_layout_ok(m, layout)) return hipErrorInvalidValue;
@@ -274,8 +498,12 @@ template <int NN>
 static hipError_t launch_series_nn(const LaunchPhase2& p, hipStream_t st) {
     const uint64_t per_block = 64ull * p.per_thread;
     const unsigned grid = (unsigned)((p.count + per_block - 1) / per_block);
-    hipLaunchKernelGGL(series_kernel<NN>, dim3(grid), dim3(64), 0, st, p.E, p.count, p.D, p.sign, p.per_thread,
-                       p.partials, p.terms);
+    if (p.fp32)
+        hipLaunchKernelGGL((series_kernel<NN, float2>), dim3(grid), dim3(64), 0, st, static_cast<const float2*>(p.E),
+                           p.count, p.D, p.sign, p.per_thread, p.partials, p.terms);
+    else
+        hipLaunchKernelGGL((series_kernel<NN, double2>), dim3(grid), dim3(64), 0, st,
+                           static_cast<const double2*>(p.E), p.count, p.D, p.sign, p.per_thread, p.partials, p.terms);
     return hipGetLastError();
 }
 

@@ -96,7 +96,7 @@ def test_validation_errors_before_any_device_work():
     _expect(-3, gbs.lhaf, nan)
     _expect(-4, gbs.lhaf, A, None, [20, 20, 20, 20, 0, 0])
     _expect(-1, gbs.lhaf, A, None, [1, -1, 1, 1, 1, 1])
-    _expect(-9, gbs.lhaf, A, None, None, gbs.GBS_FP32_COMP)
+    _expect(-1, gbs.lhaf, A, None, None, 7)  # not a gbs_precision
     _expect(-2, gbs.haf, bad)
     _expect(-1, gbs.lhaf_terms, A, [1 << 5])
     L = gbs.lib()

@@ -1,0 +1,131 @@
+"""Batched loop hafnians (persistent kernels captured in a HIP graph)
+against single evaluations and the oracle, including graph replays."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_15595_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+NORMWISE = 2e-14
+
+
+@pytest.fixture(scope="module")
+def gbs():
+    import paper_2010_15595_amd as g
+
+    g.init(0)
+    return g
+
+
+def _items(count, seed, lo=0, hi=28):
+    r = np.random.default_rng(seed)
+    dims = [int(x) for x in r.integers(lo, hi + 1, count)]
+    mats = [workloads.random_normal_symmetric(N, seed=1000 * seed + i, scale=0.5) for i, N in enumerate(dims)]
+    return dims, mats
+
+
+def _run(gbs, plan, mats):
+    import torch
+
+    dev = torch.device("cuda:0")
+    packed = torch.from_numpy(gbs.pack(mats)).to(dev)
+    out = torch.zeros(len(mats), dtype=torch.complex128, device=dev)
+    ab = torch.zeros(len(mats), dtype=torch.float64, device=dev)
+    plan.run(packed, out, ab)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ab.cpu().numpy()
+
+
+def test_batch_matches_single_evaluations_and_oracle(gbs):
+    dims, mats = _items(40, seed=1)
+    plan = gbs.BatchPlan(dims)
+    info = plan.info()
+    print(f"[batch] {info}", flush=True)
+    got, ab = _run(gbs, plan, mats)
+    worst = 0.0
+    for i, A in enumerate(mats):
+        single, d = gbs.lhaf(A, with_diag=True)
+        assert abs(got[i] - single) <= NORMWISE * d["abs_sum"] + 1e-300, (i, dims[i])
+        assert ab[i] == pytest.approx(d["abs_sum"], rel=1e-9)
+        if dims[i] <= 20:
+            ref = oracle.to_complex(oracle.lhaf_pt(A, prec="ld"))
+            assert abs(got[i] - ref) <= max(1e-10 * abs(ref), NORMWISE * ab[i])
+            worst = max(worst, abs(got[i] - ref) / max(ab[i], 1e-300))
+    print(f"[batch] worst normwise error vs oracle {worst:.2e}", flush=True)
+    plan.close()
+
+
+def test_graph_replays_are_identical(gbs):
+    import torch
+
+    dims, mats = _items(25, seed=2, lo=6, hi=30)
+    plan = gbs.BatchPlan(dims)
+    first, _ = _run(gbs, plan, mats)
+    for rep in range(3):
+        # eager work and synchronisation between replays
+        x = torch.randn(1 << 16, device="cuda:0")
+        _ = (x * x).sum().item()
+        gbs.lhaf(mats[0])
+        again, _ = _run(gbs, plan, mats)
+        assert np.array_equal(again, first), f"replay {rep} differs"
+    plan.close()
+
+
+def test_batch_chain_like_patterns(gbs):
+    """Items of the chain-like workload: expanded from one 100-mode state."""
+    st = workloads.config4(count=48)
+    mats = [gbs.expand(st["B"], st["gamma"], pat) for pat in st["patterns"]]
+    dims = [a.shape[0] for a in mats]
+    plan = gbs.BatchPlan(dims)
+    got, ab = _run(gbs, plan, mats)
+    for i, A in enumerate(mats):
+        single, d = gbs.lhaf(A, with_diag=True)
+        assert abs(got[i] - single) <= NORMWISE * d["abs_sum"], (i, dims[i])
+    plan.close()
+
+
+def test_batch_fp32_path(gbs):
+    dims, mats = _items(20, seed=3, lo=4, hi=20)
+    plan = gbs.BatchPlan(dims, prec=gbs.GBS_FP32_COMP)
+    got, ab = _run(gbs, plan, mats)
+    for i, A in enumerate(mats):
+        ref = oracle.to_complex(oracle.lhaf_pt(A, prec="ld"))
+        assert abs(got[i] - ref) <= 5e-6 * ab[i] + 1e-300, (i, dims[i])
+    plan.close()
+
+
+def test_batch_autotuned_plan(gbs):
+    dims, mats = _items(30, seed=4, lo=10, hi=30)
+    plan = gbs.BatchPlan(dims, autotune=True)
+    info = plan.info()
+    assert info["tile_subsets"] in (1024, 4096, 16384, 65536)
+    print(f"[batch autotune] tile {info['tile_subsets']}, {info['tune_ms']:.2f} ms", flush=True)
+    got, _ = _run(gbs, plan, mats)
+    for i, A in enumerate(mats):
+        single, d = gbs.lhaf(A, with_diag=True)
+        assert abs(got[i] - single) <= NORMWISE * d["abs_sum"]
+    plan.close()
+
+
+def test_batch_edge_items(gbs):
+    """Empty, one-vertex and odd-dimension items; a batch with no items."""
+    dims = [0, 1, 2, 3, 5, 0, 9, 14, 1]
+    mats = [workloads.random_normal_symmetric(N, seed=70 + i, scale=0.7) for i, N in enumerate(dims)]
+    plan = gbs.BatchPlan(dims)
+    got, ab = _run(gbs, plan, mats)
+    for i, A in enumerate(mats):
+        ref = oracle.to_complex(oracle.lhaf_dp(A)) if dims[i] > 0 else 1.0
+        assert abs(got[i] - ref) <= 1e-12 * max(1.0, abs(ref), ab[i]), (i, dims[i], got[i], ref)
+    plan.close()
+    empty = gbs.BatchPlan([])
+    assert empty.info()["items"] == 0
+    got, _ = _run(gbs, empty, [])
+    assert got.shape == (0,)
+    empty.close()
+
+
+def test_batch_rejects_bad_dims(gbs):
+    with pytest.raises(gbs.GbsError):
+        gbs.BatchPlan([10, 70])

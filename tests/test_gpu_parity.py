@@ -295,3 +295,59 @@ def test_autotune_then_parity(gbs):
     val, d = gbs.lhaf(A, with_diag=True)
     ref = oracle.to_complex(oracle.lhaf_pt(A, prec="ld"))
     assert report("after autotune N=28", val, ref, d["abs_sum"])
+
+
+# --------------------------------------------------------------------------
+# FP32-compensated path (La Budde, Newton, series and per-lane compensated
+# sums in complex FP32; Hessenberg reduction and cross-lane/final sums FP64)
+# --------------------------------------------------------------------------
+
+FP32_NORMWISE = 5e-6  # ~80 FP32 unit roundoffs of sum_S |t_S|
+
+
+@pytest.mark.parametrize("N", [4, 9, 16, 20])
+def test_fp32_path_small(gbs, N):
+    A = workloads.random_normal_symmetric(N, seed=600 + N, scale=0.5)
+    val, d = gbs.lhaf(A, prec=gbs.GBS_FP32_COMP, with_diag=True)
+    ref = oracle.to_complex(oracle.lhaf_pt(A, prec="ld"))
+    err = abs(val - ref)
+    print(f"[fp32 N={N}] rel err {err / abs(ref):.2e}, normwise {err / d['abs_sum']:.2e}, kappa {d['kappa']:.2e}",
+          flush=True)
+    assert err <= FP32_NORMWISE * d["abs_sum"]
+
+
+def test_fp32_config1(gbs):
+    st = workloads.config1()
+    val, d = gbs.lhaf(st["B"], st["gamma"], st["pattern"], prec=gbs.GBS_FP32_COMP, with_diag=True)
+    A = oracle.expand(st["B"], st["gamma"], st["pattern"])
+    ref = oracle.to_complex(oracle.lhaf_dp(A, prec="ld"))
+    print(f"[fp32 C1 N=16] rel err {abs(val - ref) / abs(ref):.2e}", flush=True)
+    assert abs(val - ref) <= FP32_NORMWISE * d["abs_sum"]
+
+
+def test_fp32_terms_match_fp64_terms(gbs):
+    st = workloads.config3(40)
+    A = oracle.expand(st["B"], st["gamma"], st["pattern"])
+    masks = _sample_masks(20, 4, seed=9)
+    t64 = gbs.lhaf_terms(A, masks)
+    t32 = gbs.lhaf_terms(A, masks, prec=gbs.GBS_FP32_COMP)
+    rel = np.abs(t32 - t64) / np.abs(t64)
+    print(f"[fp32 terms N=40] median rel {np.median(rel):.2e}, worst {np.max(rel):.2e}", flush=True)
+    assert np.median(rel) <= 1e-4
+
+
+def test_mixed_precision_report_n44(gbs):
+    """Config C5 at N = 44: FP64 and FP32-compensated against the FP64 oracle,
+    with the cancellation ratio and the speedup (reported, FP64 gated)."""
+    st = workloads.config3(44)
+    A = oracle.expand(st["B"], st["gamma"], st["pattern"])
+    v64, d64 = gbs.lhaf(A, with_diag=True)
+    v32, d32 = gbs.lhaf(A, prec=gbs.GBS_FP32_COMP, with_diag=True)
+    ref, ab = oracle.lhaf_pt(A, prec="d", with_abs=True)
+    e64 = abs(v64 - ref) / abs(ref)
+    e32 = abs(v32 - ref) / abs(ref)
+    print(f"[C5 N=44] kappa {ab / abs(ref):.2e}; fp64 rel err {e64:.2e} ({d64['kernel_ms']:.1f} ms); "
+          f"fp32-comp rel err {e32:.2e} ({d32['kernel_ms']:.1f} ms); speedup {d64['kernel_ms'] / d32['kernel_ms']:.2f}x",
+          flush=True)
+    assert abs(v64 - ref) <= NORMWISE * ab + 4e-14 * d64["abs_sum"]
+    assert np.isfinite(v32.real) and np.isfinite(v32.imag)
