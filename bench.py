@@ -85,7 +85,8 @@ def bench_batch(args, gbs):
     t0 = time.perf_counter()
     plan = gbs.BatchPlan(dims, prec=prec, autotune=not args.no_autotune)
     info = plan.info()
-    log(f"plan ({time.perf_counter() - t0:.2f} s): {info}")
+    plan_s = time.perf_counter() - t0
+    log(f"plan ({plan_s:.2f} s): {info}")
     packed = torch.from_numpy(gbs.pack(mats)).to(dev)
     out = torch.zeros(len(mats), dtype=torch.complex128, device=dev)
     ab = torch.zeros(len(mats), dtype=torch.float64, device=dev)
@@ -111,6 +112,33 @@ def bench_batch(args, gbs):
     flops_per_s = args.steps * info["yardstick_flops"] / sec
     log(f"{args.steps} replays in {gpu_ms:.1f} ms: {items_per_s:.1f} lhaf/s, {terms_per_s:.4e} subset-terms/s, "
         f"{flops_per_s / 1e12:.2f} yardstick TFLOP/s")
+    # the plain form: the same items one at a time through the single-matrix entry point
+    plain = None
+    if not args.no_plain:
+        import torch as _t
+
+        mats_dev = [_t.from_numpy(a).to(dev) for a in mats]
+        o1 = _t.zeros(1, dtype=_t.complex128, device=dev)
+        a1 = _t.zeros(1, dtype=_t.float64, device=dev)
+        pv = np.zeros(len(mats), dtype=np.complex128)
+        for a in mats_dev[:8]:
+            gbs.lhaf_device(a, o1, a1, stream, prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        outs = _t.zeros(len(mats), dtype=_t.complex128, device=dev)
+        for i, a in enumerate(mats_dev):
+            gbs.lhaf_device(a, outs[i:i + 1], None, stream, prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1)
+        pv = outs.cpu().numpy()
+        scale = np.maximum(ab.cpu().numpy(), 1e-300)
+        plain = {"lhaf_per_s": len(mats) / (pms / 1000.0), "ms": pms,
+                 "max_normwise_diff_vs_batch": float(np.max(np.abs(pv - res) / scale))}
+        log(f"plain form: {len(mats)} single lhaf_device calls in {pms:.1f} ms = {plain['lhaf_per_s']:.1f} lhaf/s; "
+            f"batch speedup {plain['ms'] / (gpu_ms / args.steps):.2f}x; max |diff|/sum|t| {plain['max_normwise_diff_vs_batch']:.2e}")
     result = {
         "metric": "loop hafnians/s and subset-terms/s, batched uneven N",
         "value": items_per_s,
@@ -136,6 +164,8 @@ def bench_batch(args, gbs):
         "subset_terms_per_s": terms_per_s,
         "yardstick_tflops": flops_per_s / 1e12,
         "pct_fp64_peak": 100.0 * flops_per_s / (FP64_PEAK_TFLOPS * 1e12),
+        "plan_seconds": plan_s,
+        "plain_form": plain,
     }
     plan.close()
     print(json.dumps(result), flush=True)
@@ -159,6 +189,7 @@ def main():
                     help="batch: 4096 loop hafnians of uneven N in [10, 36] from one 100-mode state, "
                          "one captured graph of persistent launches per step")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--no-plain", action="store_true", help="batch: skip timing the items one at a time")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch

@@ -377,9 +377,20 @@ struct Lds {
     void* ring;      // [NT][RS * RS]: last RS trailing characteristic polynomials
 };
 
-// LDS bytes of the per-subset kernel; vbytes = size of the La Budde complex type.
-__host__ __device__ constexpr size_t charpoly_lds_bytes(int W, int NT, int D, int vbytes) {
-    return (size_t)16 * (W * (64 + 2 + 16) + NT * 64) + (size_t)vbytes * NT * (64 + (D + 1) * (D + 1));
+// La Budde team layout: teams of T lanes (P Q, or 64 when a subset needs more
+// than P Q coefficient lanes); a 64-lane team serving at most 32 coefficients
+// splits the k terms over its two half-waves.
+__host__ __device__ constexpr int lb_split(int T, int D) { return (T == 64 && D + 1 <= 32) ? 2 : 1; }
+__host__ __device__ constexpr int lb_team(int G, int D) { return (G >= D + 1) ? G : 64; }
+// Team variant of a launch: 0 = (T = P Q, split 1), 1 = (64, 2), 2 = (64, 1).
+__host__ __device__ constexpr int lb_variant(int G, int D) {
+    return (lb_team(G, D) < 64) ? 0 : (lb_split(64, D) == 2 ? 1 : 2);
+}
+
+// LDS bytes of the per-subset kernel with teams of T lanes (64 / T teams);
+// vbytes = size of the La Budde complex type.  Non-decreasing in D.
+__host__ __device__ constexpr size_t charpoly_lds_bytes(int W, int T, int D, int vbytes) {
+    return (size_t)16 * (W * (64 + 2 + 16) + (64 / T) * 64) + (size_t)vbytes * (64 / T) * (64 + (D + 1) * (D + 1));
 }
 
 template <int P, int Q, int MR, int MC, int KJ>
@@ -458,8 +469,8 @@ __device__ __forceinline__ void hess_all(double2 (&a)[MR][MC], double2 (&y)[MC],
 // With split = 2 (64-lane team, D + 1 <= 32) the lanes d and d + 32 share
 // coefficient d: the low half takes odd k, the high half even k, and the two
 // partial sums are added across the halves.
-template <class V>
-__device__ __forceinline__ void labudde_step(int rho, int m, int D, int d, int half, int split, V hrr, V sub_in,
+template <class V, int SPLIT>
+__device__ __forceinline__ void labudde_step(int rho, int m, int D, int d, int half, V hrr, V sub_in,
                                              V& pik, const double2* __restrict__ rowbuf, V* __restrict__ betab,
                                              V* __restrict__ ring) {
     const int RS = D + 1;
@@ -481,19 +492,19 @@ __device__ __forceinline__ void labudde_step(int rho, int m, int D, int d, int h
         // element of poly r+k+1 at coefficient d-k-1: ring[slot(k) * RS + d - k - 1]
         int slot = (r + 2 + half) % RS;
         const V* base = ring + d - 1;
-        for (int k = 1 + half; k <= kmax; k += split) {
+        for (int k = 1 + half; k <= kmax; k += SPLIT) {
             e = vfms(betab[k], base[slot * RS - k], e);
-            slot += split;
+            slot += SPLIT;
             if (slot >= RS) slot -= RS;
         }
     }
-    if (split == 2) e = vmk<V>(swap_sum32(e.x), swap_sum32(e.y));
+    if constexpr (SPLIT == 2) e = vmk<V>(swap_sum32(e.x), swap_sum32(e.y));
     if (half == 0 && d <= D) ring[(r % RS) * RS + d] = e;
     wave_sync();
 }
 
-template <int P, int Q, int MR, int MC, int I, class V>
-__device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, int D, int d, int half, int split,
+template <int P, int Q, int MR, int MC, int I, class V, int SPLIT>
+__device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, int D, int d, int half,
                                              int pr, int pc,
                                              bool row_owner_group, double2* __restrict__ rowbuf_own,
                                              const double2* __restrict__ rowbuf, V* __restrict__ betab,
@@ -509,24 +520,36 @@ __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, 
             wave_sync();
             const V hrr = vconv<V>(rowbuf[rho]);
             const V sub_next = (rho >= 1) ? vconv<V>(rowbuf[rho - 1]) : vzero<V>();
-            labudde_step<V>(rho, m, D, d, half, split, hrr, sub, pik, rowbuf, betab, ring);
+            labudde_step<V, SPLIT>(rho, m, D, d, half, hrr, sub, pik, rowbuf, betab, ring);
             sub = sub_next;
         }
-        labudde_rows<P, Q, MR, MC, I - 1, V>(a, m, D, d, half, split, pr, pc, row_owner_group, rowbuf_own, rowbuf,
-                                             betab, ring, pik, sub);
+        labudde_rows<P, Q, MR, MC, I - 1, V, SPLIT>(a, m, D, d, half, pr, pc, row_owner_group, rowbuf_own, rowbuf,
+                                                    betab, ring, pik, sub);
     }
 }
+
+// Wavefronts per SIMD the register allocation of each instance is held to.
+#ifdef GBS_WPE_FORCE
+__host__ __device__ constexpr int charpoly_waves_per_simd(int, int, int, int, bool) { return GBS_WPE_FORCE; }
+#else
+__host__ __device__ constexpr int charpoly_waves_per_simd(int P, int Q, int MR, int MC, bool batch) {
+    return 1;
+}
+#endif
 
 // One wavefront's work: the W subsets with local indices first .. first+W-1
 // of a run of `count` subsets of size s (colex ranks rank0 + index, or the
 // explicit masks), each written to Eout + index * 2(D+1).
 // V: complex type of the La Budde recurrence and of the output (double2 for
 // the FP64 path, float2 for the FP32 path; the Hessenberg reduction is FP64).
-template <int P, int Q, int MR, int MC, class V>
+// La Budde teams have TEAM lanes (P Q, or 64 when a subset needs more than
+// P Q coefficient lanes) and SPLIT = lb_split(TEAM, D); both fixed per launch.
+template <int P, int Q, int MR, int MC, class V, int TEAM, int SPLIT>
 __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, const double2* __restrict__ dvec, int Np,
                                               int s, uint64_t rank0, uint64_t count, uint64_t first,
                                               const uint64_t* __restrict__ masks, const uint64_t* __restrict__ binom,
-                                              int D, int T, V* __restrict__ Eout, double2* __restrict__ lds) {
+                                              int D, V* __restrict__ Eout, double2* __restrict__ lds) {
+    constexpr int T = TEAM;
     constexpr int G = P * Q;
     constexpr int W = 64 / G;
     const int lane = threadIdx.x;
@@ -535,7 +558,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     const int pc = (lane / P) % Q;
     const int n = Np >> 1;
     const int m = 2 * s;
-    const int NT = 64 / T;
+    constexpr int NT = 64 / T;
     const int RS = D + 1;
     Lds L;
     L.vbuf = lds;
@@ -643,9 +666,8 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     // La Budde over the trailing blocks of H' (size m + 1).  Team t of T lanes
     // handles group t + NT * pass; lane d of the team holds coefficient d.
     const int team = lane / T;
-    const int split = (T == 64 && D + 1 <= 32) ? 2 : 1;
-    const int d = lane % (T / split);
-    const int half = (lane % T) / (T / split);
+    const int d = lane % (T / SPLIT);
+    const int half = (lane % T) / (T / SPLIT);
     const int Mp = m + 1;
     for (int pass = 0; pass < W / NT; ++pass) {
         const int gt = pass * NT + team;          // group served by my team
@@ -658,8 +680,8 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         V pik = (d == 0) ? vone<V>() : vzero<V>();
         V sub = vzero<V>();
         wave_sync();
-        labudde_rows<P, Q, MR, MC, MR - 1, V>(a, m, D, d, half, split, pr, pc, own, rowbuf_own, rowbuf, betab, ring,
-                                              pik, sub);
+        labudde_rows<P, Q, MR, MC, MR - 1, V, SPLIT>(a, m, D, d, half, pr, pc, own, rowbuf_own, rowbuf, betab, ring,
+                                                     pik, sub);
         // border row: H'[0][k] = y''_{k-1}, H'[0][0] = 0, H'[1][0] = alpha
         if (own && pr == 0) {
 #pragma unroll
@@ -667,7 +689,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         }
         wave_sync();
         const V alpha_t = vconv<V>(L.misc[gt * 2 + 1]);
-        labudde_step<V>(-1, m, D, d, half, split, vzero<V>(), alpha_t, pik, rowbuf, betab, ring);
+        labudde_step<V, SPLIT>(-1, m, D, d, half, vzero<V>(), alpha_t, pik, rowbuf, betab, ring);
         const uint64_t gi = first + gt;
         if (half == 0 && d <= D && gi < count) {
             V* out = Eout + gi * (uint64_t)(2 * RS);
@@ -679,23 +701,22 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
 }
 
 
-template <int P, int Q, int MR, int MC, class V>
-__global__ void __launch_bounds__(64) charpoly_kernel(const double2* __restrict__ A0, const double2* __restrict__ dvec,
-                                                      int Np, int s, uint64_t rank0, uint64_t count,
-                                                      const uint64_t* __restrict__ masks,
-                                                      const uint64_t* __restrict__ binom, int D, int T,
-                                                      V* __restrict__ Eout) {
+template <int P, int Q, int MR, int MC, class V, int TEAM, int SPLIT>
+__global__ void __launch_bounds__(64, charpoly_waves_per_simd(P, Q, MR, MC, false))
+    charpoly_kernel(const double2* __restrict__ A0, const double2* __restrict__ dvec, int Np, int s, uint64_t rank0,
+                    uint64_t count, const uint64_t* __restrict__ masks, const uint64_t* __restrict__ binom, int D,
+                    V* __restrict__ Eout) {
     extern __shared__ double2 lds[];
     constexpr int W = 64 / (P * Q);
-    charpoly_wave<P, Q, MR, MC, V>(A0, dvec, Np, s, rank0, count, (uint64_t)blockIdx.x * W, masks, binom, D, T, Eout,
-                                   lds);
+    charpoly_wave<P, Q, MR, MC, V, TEAM, SPLIT>(A0, dvec, Np, s, rank0, count, (uint64_t)blockIdx.x * W, masks, binom,
+                                                D, Eout, lds);
 }
 
 // Persistent form for batches: every wavefront takes tiles from `tiles`
 // (largest first) through a device counter until none is left, and runs all
 // subsets of each tile.  The counter is cleared by the caller's fill kernel.
-template <int P, int Q, int MR, int MC, class V>
-__global__ void __launch_bounds__(64) charpoly_batch_kernel(const BatchTile* __restrict__ tiles, int ntiles,
+template <int P, int Q, int MR, int MC, class V, int TEAM, int SPLIT>
+__global__ void __launch_bounds__(64, charpoly_waves_per_simd(P, Q, MR, MC, true)) charpoly_batch_kernel(const BatchTile* __restrict__ tiles, int ntiles,
                                                             const BatchItem* __restrict__ items,
                                                             const uint64_t* __restrict__ binom,
                                                             unsigned* __restrict__ counter, V* __restrict__ Ebase) {
@@ -705,15 +726,18 @@ __global__ void __launch_bounds__(64) charpoly_batch_kernel(const BatchTile* __r
     for (;;) {
         int t = 0;
         if (threadIdx.x == 0) t = (int)atomicAdd(counter, 1u);
-        t = __shfl(t, 0);
+        // readfirstlane keeps the tile index, and everything loaded from the
+        // tile and item records, in scalar registers
+        t = __builtin_amdgcn_readfirstlane(t);
         if (t >= ntiles) break;
         const BatchTile tl = tiles[t];
         const BatchItem it = items[tl.item];
         const int D = it.n + 1;
-        const int T = (G >= D + 1) ? G : 64;
+        // the plan groups tiles by La Budde team layout; never taken
+        if (((G >= D + 1) ? G : 64) != TEAM || lb_split(TEAM, D) != SPLIT) continue;
         for (uint64_t first = 0; first < tl.count; first += W)
-            charpoly_wave<P, Q, MR, MC, V>(it.A0, it.dvec, it.Np, tl.s, tl.rank0, tl.count, first, nullptr, binom, D,
-                                           T, Ebase + tl.eoff, lds);
+            charpoly_wave<P, Q, MR, MC, V, TEAM, SPLIT>(it.A0, it.dvec, it.Np, tl.s, tl.rank0, tl.count, first,
+                                                        nullptr, binom, D, Ebase + tl.eoff, lds);
         wave_sync();
     }
 }

@@ -65,12 +65,15 @@ struct SeriesBlock {
 };
 
 // Persistent per-subset kernel over tiles that all use grid `layout` with the
-// same (MR, MC) as subsets of size s_rep; D_max sizes the LDS.
-hipError_t launch_charpoly_batch(int layout, int s_rep, int D_max, int fp32, const BatchTile* tiles, int ntiles,
-                                 const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
-                                 int grid, hipStream_t st);
+// same (MR, MC) as subsets of size s_rep and the same La Budde team variant;
+// D_max sizes the LDS.
+hipError_t launch_charpoly_batch(int layout, int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles,
+                                 int ntiles, const BatchItem* items, const uint64_t* binom, unsigned* counter,
+                                 void* Ebase, int grid, hipStream_t st);
 // Kernel instance id (layout, MR, MC) of subsets of size s under `layout`.
 int charpoly_instance(int layout, int s);
+// La Budde team variant (0, 1, 2) of an n-pair loop hafnian under `layout`.
+int charpoly_variant(int layout, int n);
 hipError_t launch_series_batch(int n, int fp32, const SeriesBlock* blocks, int nblocks, const BatchTile* tiles,
                                const BatchItem* items, const void* Ebase, int per_thread, double* partials,
                                hipStream_t st);

@@ -400,13 +400,13 @@ bool charpoly_layout_ok(int m, int layout) {
 
 int charpoly_default_layout(int m) { return m <= 16 ? kLayout44 : (m <= 32 ? kLayout84 : kLayout88); }
 
-hipError_t launch_charpoly_batch_l44(int s_rep, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+hipError_t launch_charpoly_batch_l44(int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
                                      const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
                                      int grid, hipStream_t st);
-hipError_t launch_charpoly_batch_l84(int s_rep, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+hipError_t launch_charpoly_batch_l84(int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
                                      const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
                                      int grid, hipStream_t st);
-hipError_t launch_charpoly_batch_l88(int s_rep, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+hipError_t launch_charpoly_batch_l88(int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
                                      const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
                                      int grid, hipStream_t st);
 
@@ -419,17 +419,23 @@ int charpoly_instance(int layout, int s) {
     }
 }
 
-hipError_t launch_charpoly_batch(int layout, int s_rep, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+int charpoly_variant(int layout, int n) {
+    const int G = (layout == kLayout44) ? 16 : (layout == kLayout84) ? 32 : 64;
+    return lb_variant(G, n + 1);
+}
+
+hipError_t launch_charpoly_batch(int layout, int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles,
+                                 int ntiles,
                                  const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
                                  int grid, hipStream_t st) {
     if (!charpoly_layout_ok(2 * s_rep, layout)) return hipErrorInvalidValue;
     switch (layout) {
         case kLayout44:
-            return launch_charpoly_batch_l44(s_rep, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
+            return launch_charpoly_batch_l44(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
         case kLayout84:
-            return launch_charpoly_batch_l84(s_rep, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
+            return launch_charpoly_batch_l84(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
         default:
-            return launch_charpoly_batch_l88(s_rep, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
+            return launch_charpoly_batch_l88(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
     }
 }
 
