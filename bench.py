@@ -22,6 +22,30 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU (vector FMA)
 
+# HBM bytes per launch of the dominant per-subset kernel on the N = 50 step, from
+# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs scaled by the same counters
+# on a plain 256 MiB device copy (fetch x2.0, write x1.0); the command and raw
+# figures are in profiles/charpoly_n50_traffic.md.  Valid only for the kernel
+# sources hashed here: any change to them reports null until re-measured.
+TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_amd/csrc/charpoly_l88.hip")
+TRAFFIC = None  # {"sha256": ..., "kernel": ..., "fetch_bytes": ..., "write_bytes": ..., "subsets": ...}
+
+
+def sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_entry():
+    if TRAFFIC is None or TRAFFIC["sha256"] != sources_sha256():
+        return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -183,6 +207,8 @@ def main():
                     help="fp32comp: La Budde, series and per-lane sums in complex FP32 (Hessenberg FP64)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the lane-grid autotuner (use the heuristic or GBS_AUTOTUNE_CACHE)")
+    ap.add_argument("--print-source-hash", action="store_true",
+                    help="print the hash of the kernel sources the traffic figures are tied to")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (HBM counter calibration)")
     ap.add_argument("--workload", choices=["n50", "batch"], default="n50",
@@ -191,6 +217,9 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--no-plain", action="store_true", help="batch: skip timing the items one at a time")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(sources_sha256())
+        return
     if args.copy_calibration:
         import torch
 
@@ -309,7 +338,9 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None,
-            "traffic": None,
+            "traffic": traffic_entry(),
+            "traffic_unit": "HBM bytes per launch of the dominant instance (8x8 lanes, MR = MC = 4)",
+            "algorithmic_bytes_per_subset": 2 * (n + 2) * 16,
             "launches_per_step": prof["charpoly_launches"] / args.steps,
             "kernel_ms_per_step": prof["charpoly_ms"] / args.steps,
         },
