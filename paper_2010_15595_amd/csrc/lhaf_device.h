@@ -374,7 +374,7 @@ struct Lds {
     int* idx;        // [W][64]: vertex indices of the subset
     double2* rowbuf; // [NT][64]: current row of H' (La Budde)
     void* betab;     // [NT][64]: beta_k of the current row (La Budde type)
-    void* ring;      // [NT][RS * RS]: last RS trailing characteristic polynomials
+    void* ring;      // [NT][RS * RS]: last RS trailing characteristic polynomials (anti-diagonal rows)
 };
 
 // La Budde team layout: teams of T lanes (P Q, or 64 when a subset needs more
@@ -481,25 +481,33 @@ __device__ __forceinline__ void labudde_step(int rho, int m, int D, int d, int h
     const int K = min(D - 1, m - rho - 1);
     if (half == 0 && d >= 1 && d <= K) betab[d] = vmul(vconv<V>(rowbuf[rho + d]), pik);
     wave_sync();
+    // Ring layout: coefficient c of the trailing polynomial of row u is stored at
+    // ring[((u + c) % RS) RS + c].  Every term of lane d in this step reads
+    // coefficient d - k - 1 of row r + k + 1, i.e. the same ring row (r + d) % RS,
+    // walking down its columns; no slot wraps inside the k loop.
+    int row = r % RS + d;
+    if (row >= RS) row -= RS;
     V e = vzero<V>();
     if (d <= D) {
-        const V* prev = ring + ((r + 1) % RS) * RS;
         if (half == 0) {
-            e = prev[d];
-            if (d >= 1) e = vfms(hrr, prev[d - 1], e);
+            const int rowp = (row + 1 == RS) ? 0 : row + 1;
+            e = ring[rowp * RS + d];
+            if (d >= 1) e = vfms(hrr, ring[row * RS + d - 1], e);
         }
         const int kmax = min(K, d - 1);
-        // element of poly r+k+1 at coefficient d-k-1: ring[slot(k) * RS + d - k - 1]
-        int slot = (r + 2 + half) % RS;
-        const V* base = ring + d - 1;
-        for (int k = 1 + half; k <= kmax; k += SPLIT) {
-            e = vfms(betab[k], base[slot * RS - k], e);
-            slot += SPLIT;
-            if (slot >= RS) slot -= RS;
+        if (kmax >= 1 + half) {
+            const int nk = (kmax - 1 - half) / SPLIT + 1;
+            const V* rp = ring + row * RS + d - 2 - half;
+            const V* bp = betab + 1 + half;
+            for (int j = 0; j < nk; ++j) {
+                e = vfms(bp[0], rp[0], e);
+                bp += SPLIT;
+                rp -= SPLIT;
+            }
         }
     }
     if constexpr (SPLIT == 2) e = vmk<V>(swap_sum32(e.x), swap_sum32(e.y));
-    if (half == 0 && d <= D) ring[(r % RS) * RS + d] = e;
+    if (half == 0 && d <= D) ring[row * RS + d] = e;
     wave_sync();
 }
 
@@ -676,7 +684,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         double2* rowbuf = L.rowbuf + team * 64;
         V* betab = reinterpret_cast<V*>(L.betab) + team * 64;
         V* ring = reinterpret_cast<V*>(L.ring) + team * RS * RS;
-        if (half == 0 && d < RS) ring[(Mp % RS) * RS + d] = (d == 0) ? vone<V>() : vzero<V>();
+        if (half == 0 && d < RS) ring[((Mp + d) % RS) * RS + d] = (d == 0) ? vone<V>() : vzero<V>();
         V pik = (d == 0) ? vone<V>() : vzero<V>();
         V sub = vzero<V>();
         wave_sync();
@@ -693,8 +701,8 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         const uint64_t gi = first + gt;
         if (half == 0 && d <= D && gi < count) {
             V* out = Eout + gi * (uint64_t)(2 * RS);
-            out[d] = ring[(1 % RS) * RS + d];
-            out[RS + d] = ring[d];
+            out[d] = ring[((1 + d) % RS) * RS + d];  // row 1: det(xI - C)
+            out[RS + d] = ring[d * RS + d];          // row 0: det(xI - C')
         }
         wave_sync();
     }
