@@ -308,7 +308,8 @@ gbs_status plan_build_into(DevCtx* c, const std::vector<int>& dims, bool fp32, i
             const int grid = std::min(L.ntiles, kPersistentWaves);
             HIP_TRY(gbs::launch_charpoly_batch(L.layout, L.s_rep, L.variant, p->max_n + 1, fp32 ? 1 : 0,
                                                p->tiles + L.tile_begin,
-                                               L.ntiles, p->items, c->binom, p->counters + L.counter, E, grid, bs));
+                                               L.ntiles, p->items, c->binom, c->lbmap, p->counters + L.counter, E,
+                                               grid, bs));
             hipEvent_t ej;
             HIP_TRY(new_event(&ej));
             HIP_TRY(hipEventRecord(ej, bs));

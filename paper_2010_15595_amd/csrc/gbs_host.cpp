@@ -118,6 +118,10 @@ gbs_status ctx_create(int device, DevCtx** out) {
         for (int b = 0; b < gbs::kBinomStride; ++b) tab[a * gbs::kBinomStride + b] = binom_host(a, b);
     HIP_TRY(hipMalloc((void**)&c->binom, tab.size() * sizeof(uint64_t)));
     HIP_TRY(hipMemcpy(c->binom, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    std::vector<int4> lbt(gbs::kLbTableEntries);
+    gbs::lb_fill_table(lbt.data());
+    HIP_TRY(hipMalloc((void**)&c->lbmap, lbt.size() * sizeof(int4)));
+    HIP_TRY(hipMemcpy(c->lbmap, lbt.data(), lbt.size() * sizeof(int4), hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc((void**)&c->A0, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
     HIP_TRY(hipMalloc((void**)&c->dvec, sizeof(double2) * GBS_MAX_DIM));
     HIP_TRY(hipMalloc((void**)&c->Ain, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
@@ -138,6 +142,7 @@ void ctx_destroy(DevCtx* c) {
     hipSetDevice(c->device);
     if (c->stream) hipStreamSynchronize(c->stream);
     hipFree(c->binom);
+    hipFree(c->lbmap);
     hipFree(c->A0);
     hipFree(c->dvec);
     hipFree(c->Ain);
@@ -260,7 +265,7 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
         const double sign = ((n - s) & 1) ? -1.0 : 1.0;
         for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
             const uint64_t len = std::min(kChunk, cnt - st0);
-            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, c->E, fp32 ? 1 : 0};
+            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, c->E, fp32 ? 1 : 0, c->lbmap};
             const int lay = layout_for(c, n, s);
             HIP_TRY(timed_launch(kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
                                  [&] { return gbs::launch_charpoly(p1, lay, st); }));
@@ -577,7 +582,7 @@ gbs_status gbs_lhaf_terms(const gbs_z* A, int32_t N, int64_t lda, const uint64_t
             st = ensure_buffer((void**)&c->partials, &c->partials_cap, nblk * 5, sizeof(double));
             if (st != GBS_OK) return st;
             HIP_TRY(hipMemcpyAsync(c->masks, grp.data() + off, sizeof(uint64_t) * len, hipMemcpyHostToDevice, c->stream));
-            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, c->E, fp32 ? 1 : 0};
+            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, c->E, fp32 ? 1 : 0, c->lbmap};
             HIP_TRY(gbs::launch_charpoly(p1, layout_for(c, n, s), c->stream));
             gbs::LaunchPhase2 p2{c->E, fp32 ? 1 : 0, len, D, ((n - s) & 1) ? -1.0 : 1.0, kPerThread, c->partials,
                                  c->terms};
@@ -746,7 +751,7 @@ gbs_status autotune_impl(DevCtx* c, int n, gbs_tune_report* rep) {
         int best_lay = gbs::charpoly_default_layout(2 * s);
         for (int lay = 0; lay < gbs::kNumLayouts; ++lay) {
             if (!gbs::charpoly_layout_ok(2 * s, lay)) continue;
-            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, nullptr, c->binom, D, c->E, 0};
+            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, nullptr, c->binom, D, c->E, 0, c->lbmap};
             HIP_TRY(gbs::launch_charpoly(p1, lay, c->stream));  // warm-up
             HIP_TRY(hipEventRecord(c->t0, c->stream));
             const int reps = 3;

@@ -34,6 +34,7 @@ struct DevCtx {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr, t0 = nullptr, t1 = nullptr;
     uint64_t* binom = nullptr;
+    int4* lbmap = nullptr;      // La Budde lane maps (gbs::lb_fill_table)
     double2* A0 = nullptr;      // 64 x 64
     double2* dvec = nullptr;    // 64
     double2* Ain = nullptr;     // host-call staging, 64 x 64

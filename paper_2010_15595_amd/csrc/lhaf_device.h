@@ -75,6 +75,10 @@ __device__ __forceinline__ double dpp_mov(double x) {
     int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
 
 // Sum over the 8 lanes of an aligned octet; every lane of the octet gets the
 // same bits (each butterfly level adds the same two operands, commuted).
@@ -378,13 +382,18 @@ struct Lds {
 };
 
 // La Budde team layout: teams of T lanes (P Q, or 64 when a subset needs more
-// than P Q coefficient lanes); a 64-lane team serving at most 32 coefficients
-// splits the k terms over its two half-waves.
-__host__ __device__ constexpr int lb_split(int T, int D) { return (T == 64 && D + 1 <= 32) ? 2 : 1; }
+// than P Q coefficient lanes).  Within a team, coefficient d gets a group of
+// g_d lanes (a power of two, at most 4) that split its terms k = 1..d-1; the
+// lane map (d, g_d, first k, last k) per team lane is a table built on the host
+// for every (T, D), so the longest lane carries about D^2 / (2 T) terms instead
+// of D - 1.
 __host__ __device__ constexpr int lb_team(int G, int D) { return (G >= D + 1) ? G : 64; }
-// Team variant of a launch: 0 = (T = P Q, split 1), 1 = (64, 2), 2 = (64, 1).
-__host__ __device__ constexpr int lb_variant(int G, int D) {
-    return (lb_team(G, D) < 64) ? 0 : (lb_split(64, D) == 2 ? 1 : 2);
+// Team variant of a launch: 0 = teams of P Q lanes, 1 = one team of 64 lanes.
+__host__ __device__ constexpr int lb_variant(int G, int D) { return (lb_team(G, D) < 64) ? 0 : 1; }
+constexpr int kLbMaxD = kMaxPairs + 2;  // D = n + 1 <= 33
+// Offset (in int4 entries) of the lane map of teams of T lanes for D.
+__host__ __device__ constexpr int lb_table_offset(int T, int D) {
+    return (((T == 16) ? 0 : (T == 32) ? 1 : 2) * kLbMaxD + D) * 64;
 }
 
 // LDS bytes of the per-subset kernel with teams of T lanes (64 / T teams);
@@ -464,56 +473,61 @@ __device__ __forceinline__ void hess_all(double2 (&a)[MR][MC], double2 (&y)[MC],
 }
 
 // One La Budde step (team-local): row r = rho + 1 of H' is in rowbuf at
-// index rho + k for H'[r][r + k]; sub_in = H'[r + 1][r].  Team lane d updates
-// coefficient d of the trailing polynomial of rows r.. (ring slot r % RS).
-// With split = 2 (64-lane team, D + 1 <= 32) the lanes d and d + 32 share
-// coefficient d: the low half takes odd k, the high half even k, and the two
-// partial sums are added across the halves.
-template <class V, int SPLIT>
-__device__ __forceinline__ void labudde_step(int rho, int m, int D, int d, int half, V hrr, V sub_in,
-                                             V& pik, const double2* __restrict__ rowbuf, V* __restrict__ betab,
+// index rho + k for H'[r][r + k]; sub_in = H'[r + 1][r].  Team lane tl keeps
+// pi_{r,tl} and writes beta_{tl}; under the lane map mp = (d, g, klo, khi) it
+// sums the terms klo..khi of coefficient d; the group's partial sums are added
+// across its lanes and the first lane stores coefficient d.  gmax: the largest
+// group of the team (the same in every lane).
+template <class V>
+__device__ __forceinline__ void labudde_step(int rho, int m, int D, int tl, int4 mp, int gmax,
+                                             typename CxT<V>::S m1, typename CxT<V>::S m2, V hrr, V sub_in, V& pik,
+                                             const double2* __restrict__ rowbuf, V* __restrict__ betab,
                                              V* __restrict__ ring) {
     const int RS = D + 1;
     const int r = rho + 1;
     // pi_{r,k} = H'[r+1][r] pi_{r+1,k-1} (lane shift by one), pi_{r,0} = 1
     const V sh = vmk<V>(shr1(pik.x), shr1(pik.y));
-    pik = (d == 0) ? vone<V>() : vmul(sub_in, sh);
+    pik = (tl == 0) ? vone<V>() : vmul(sub_in, sh);
     const int K = min(D - 1, m - rho - 1);
-    if (half == 0 && d >= 1 && d <= K) betab[d] = vmul(vconv<V>(rowbuf[rho + d]), pik);
+    if (tl >= 1 && tl <= K) betab[tl] = vmul(vconv<V>(rowbuf[rho + tl]), pik);
     wave_sync();
     // Ring layout: coefficient c of the trailing polynomial of row u is stored at
-    // ring[((u + c) % RS) RS + c].  Every term of lane d in this step reads
+    // ring[((u + c) % RS) RS + c].  Every term of coefficient d in this step reads
     // coefficient d - k - 1 of row r + k + 1, i.e. the same ring row (r + d) % RS,
     // walking down its columns; no slot wraps inside the k loop.
+    const int d = mp.x;
     int row = r % RS + d;
     if (row >= RS) row -= RS;
+    const bool lead = (tl & (mp.y - 1)) == 0;
     V e = vzero<V>();
-    if (d <= D) {
-        if (half == 0) {
+    if (d >= 0) {
+        if (lead) {
             const int rowp = (row + 1 == RS) ? 0 : row + 1;
             e = ring[rowp * RS + d];
             if (d >= 1) e = vfms(hrr, ring[row * RS + d - 1], e);
         }
-        const int kmax = min(K, d - 1);
-        if (kmax >= 1 + half) {
-            const int nk = (kmax - 1 - half) / SPLIT + 1;
-            const V* rp = ring + row * RS + d - 2 - half;
-            const V* bp = betab + 1 + half;
-            for (int j = 0; j < nk; ++j) {
-                e = vfms(bp[0], rp[0], e);
-                bp += SPLIT;
-                rp -= SPLIT;
-            }
+        const int kend = min(mp.w, min(K, d - 1));
+        const V* rp = ring + row * RS + d - 1 - mp.z;
+        const V* bp = betab + mp.z;
+        for (int k = mp.z; k <= kend; ++k) {
+            e = vfms(bp[0], rp[0], e);
+            ++bp;
+            --rp;
         }
     }
-    if constexpr (SPLIT == 2) e = vmk<V>(swap_sum32(e.x), swap_sum32(e.y));
-    if (half == 0 && d <= D) ring[row * RS + d] = e;
+    // group sums: groups are aligned blocks of 1, 2 or 4 lanes; m1 = 1 in groups
+    // of 2 or more, m2 = 1 in groups of 4, else 0 (butterfly over lane ^ 1, ^ 2)
+    if (gmax > 1) {
+        e = vmk<V>(fma(m1, dpp_mov<0xB1>(e.x), e.x), fma(m1, dpp_mov<0xB1>(e.y), e.y));
+        if (gmax > 2) e = vmk<V>(fma(m2, dpp_mov<0x4E>(e.x), e.x), fma(m2, dpp_mov<0x4E>(e.y), e.y));
+    }
+    if (lead && d >= 0) ring[row * RS + d] = e;
     wave_sync();
 }
 
-template <int P, int Q, int MR, int MC, int I, class V, int SPLIT>
-__device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, int D, int d, int half,
-                                             int pr, int pc,
+template <int P, int Q, int MR, int MC, int I, class V>
+__device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, int D, int tl, int4 mp, int gmax,
+                                             typename CxT<V>::S m1, typename CxT<V>::S m2, int pr, int pc,
                                              bool row_owner_group, double2* __restrict__ rowbuf_own,
                                              const double2* __restrict__ rowbuf, V* __restrict__ betab,
                                              V* __restrict__ ring, V& pik, V& sub) {
@@ -528,11 +542,11 @@ __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, 
             wave_sync();
             const V hrr = vconv<V>(rowbuf[rho]);
             const V sub_next = (rho >= 1) ? vconv<V>(rowbuf[rho - 1]) : vzero<V>();
-            labudde_step<V, SPLIT>(rho, m, D, d, half, hrr, sub, pik, rowbuf, betab, ring);
+            labudde_step<V>(rho, m, D, tl, mp, gmax, m1, m2, hrr, sub, pik, rowbuf, betab, ring);
             sub = sub_next;
         }
-        labudde_rows<P, Q, MR, MC, I - 1, V, SPLIT>(a, m, D, d, half, pr, pc, row_owner_group, rowbuf_own, rowbuf,
-                                                    betab, ring, pik, sub);
+        labudde_rows<P, Q, MR, MC, I - 1, V>(a, m, D, tl, mp, gmax, m1, m2, pr, pc, row_owner_group, rowbuf_own,
+                                             rowbuf, betab, ring, pik, sub);
     }
 }
 
@@ -551,12 +565,13 @@ __host__ __device__ constexpr int charpoly_waves_per_simd(int P, int Q, int MR, 
 // V: complex type of the La Budde recurrence and of the output (double2 for
 // the FP64 path, float2 for the FP32 path; the Hessenberg reduction is FP64).
 // La Budde teams have TEAM lanes (P Q, or 64 when a subset needs more than
-// P Q coefficient lanes) and SPLIT = lb_split(TEAM, D); both fixed per launch.
-template <int P, int Q, int MR, int MC, class V, int TEAM, int SPLIT>
+// P Q coefficient lanes), fixed per launch; lbm is the lane map of (TEAM, D).
+template <int P, int Q, int MR, int MC, class V, int TEAM>
 __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, const double2* __restrict__ dvec, int Np,
                                               int s, uint64_t rank0, uint64_t count, uint64_t first,
                                               const uint64_t* __restrict__ masks, const uint64_t* __restrict__ binom,
-                                              int D, V* __restrict__ Eout, double2* __restrict__ lds) {
+                                              int D, const int4* __restrict__ lbm, V* __restrict__ Eout,
+                                              double2* __restrict__ lds) {
     constexpr int T = TEAM;
     constexpr int G = P * Q;
     constexpr int W = 64 / G;
@@ -674,8 +689,12 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     // La Budde over the trailing blocks of H' (size m + 1).  Team t of T lanes
     // handles group t + NT * pass; lane d of the team holds coefficient d.
     const int team = lane / T;
-    const int d = lane % (T / SPLIT);
-    const int half = (lane % T) / (T / SPLIT);
+    const int tl = lane % T;
+    const int4 mp = lbm[tl];
+    const int gmax = __builtin_amdgcn_readfirstlane(mp.y);  // team lane 0 leads the largest group
+    using S = typename CxT<V>::S;
+    const S m1 = (mp.y >= 2) ? (S)1 : (S)0;
+    const S m2 = (mp.y >= 4) ? (S)1 : (S)0;
     const int Mp = m + 1;
     for (int pass = 0; pass < W / NT; ++pass) {
         const int gt = pass * NT + team;          // group served by my team
@@ -684,12 +703,12 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         double2* rowbuf = L.rowbuf + team * 64;
         V* betab = reinterpret_cast<V*>(L.betab) + team * 64;
         V* ring = reinterpret_cast<V*>(L.ring) + team * RS * RS;
-        if (half == 0 && d < RS) ring[((Mp + d) % RS) * RS + d] = (d == 0) ? vone<V>() : vzero<V>();
-        V pik = (d == 0) ? vone<V>() : vzero<V>();
+        if (tl < RS) ring[((Mp + tl) % RS) * RS + tl] = (tl == 0) ? vone<V>() : vzero<V>();
+        V pik = (tl == 0) ? vone<V>() : vzero<V>();
         V sub = vzero<V>();
         wave_sync();
-        labudde_rows<P, Q, MR, MC, MR - 1, V, SPLIT>(a, m, D, d, half, pr, pc, own, rowbuf_own, rowbuf, betab, ring,
-                                                     pik, sub);
+        labudde_rows<P, Q, MR, MC, MR - 1, V>(a, m, D, tl, mp, gmax, m1, m2, pr, pc, own, rowbuf_own, rowbuf, betab,
+                                              ring, pik, sub);
         // border row: H'[0][k] = y''_{k-1}, H'[0][0] = 0, H'[1][0] = alpha
         if (own && pr == 0) {
 #pragma unroll
@@ -697,36 +716,37 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         }
         wave_sync();
         const V alpha_t = vconv<V>(L.misc[gt * 2 + 1]);
-        labudde_step<V, SPLIT>(-1, m, D, d, half, vzero<V>(), alpha_t, pik, rowbuf, betab, ring);
+        labudde_step<V>(-1, m, D, tl, mp, gmax, m1, m2, vzero<V>(), alpha_t, pik, rowbuf, betab, ring);
         const uint64_t gi = first + gt;
-        if (half == 0 && d <= D && gi < count) {
+        if (tl <= D && gi < count) {
             V* out = Eout + gi * (uint64_t)(2 * RS);
-            out[d] = ring[((1 + d) % RS) * RS + d];  // row 1: det(xI - C)
-            out[RS + d] = ring[d * RS + d];          // row 0: det(xI - C')
+            out[tl] = ring[((1 + tl) % RS) * RS + tl];  // row 1: det(xI - C)
+            out[RS + tl] = ring[tl * RS + tl];          // row 0: det(xI - C')
         }
         wave_sync();
     }
 }
 
 
-template <int P, int Q, int MR, int MC, class V, int TEAM, int SPLIT>
+template <int P, int Q, int MR, int MC, class V, int TEAM>
 __global__ void __launch_bounds__(64, charpoly_waves_per_simd(P, Q, MR, MC, false))
     charpoly_kernel(const double2* __restrict__ A0, const double2* __restrict__ dvec, int Np, int s, uint64_t rank0,
                     uint64_t count, const uint64_t* __restrict__ masks, const uint64_t* __restrict__ binom, int D,
-                    V* __restrict__ Eout) {
+                    const int4* __restrict__ lbm, V* __restrict__ Eout) {
     extern __shared__ double2 lds[];
     constexpr int W = 64 / (P * Q);
-    charpoly_wave<P, Q, MR, MC, V, TEAM, SPLIT>(A0, dvec, Np, s, rank0, count, (uint64_t)blockIdx.x * W, masks, binom,
-                                                D, Eout, lds);
+    charpoly_wave<P, Q, MR, MC, V, TEAM>(A0, dvec, Np, s, rank0, count, (uint64_t)blockIdx.x * W, masks, binom, D, lbm,
+                                         Eout, lds);
 }
 
 // Persistent form for batches: every wavefront takes tiles from `tiles`
 // (largest first) through a device counter until none is left, and runs all
 // subsets of each tile.  The counter is cleared by the caller's fill kernel.
-template <int P, int Q, int MR, int MC, class V, int TEAM, int SPLIT>
+template <int P, int Q, int MR, int MC, class V, int TEAM>
 __global__ void __launch_bounds__(64, charpoly_waves_per_simd(P, Q, MR, MC, true)) charpoly_batch_kernel(const BatchTile* __restrict__ tiles, int ntiles,
                                                             const BatchItem* __restrict__ items,
                                                             const uint64_t* __restrict__ binom,
+                                                            const int4* __restrict__ lbmap,
                                                             unsigned* __restrict__ counter, V* __restrict__ Ebase) {
     extern __shared__ double2 lds[];
     constexpr int G = P * Q;
@@ -741,11 +761,11 @@ __global__ void __launch_bounds__(64, charpoly_waves_per_simd(P, Q, MR, MC, true
         const BatchTile tl = tiles[t];
         const BatchItem it = items[tl.item];
         const int D = it.n + 1;
-        // the plan groups tiles by La Budde team layout; never taken
-        if (((G >= D + 1) ? G : 64) != TEAM || lb_split(TEAM, D) != SPLIT) continue;
+        if (lb_team(G, D) != TEAM) continue;  // the plan groups tiles by team layout; never taken
+        const int4* lbm = lbmap + lb_table_offset(TEAM, D);
         for (uint64_t first = 0; first < tl.count; first += W)
-            charpoly_wave<P, Q, MR, MC, V, TEAM, SPLIT>(it.A0, it.dvec, it.Np, tl.s, tl.rank0, tl.count, first,
-                                                        nullptr, binom, D, Ebase + tl.eoff, lds);
+            charpoly_wave<P, Q, MR, MC, V, TEAM>(it.A0, it.dvec, it.Np, tl.s, tl.rank0, tl.count, first, nullptr,
+                                                 binom, D, lbm, Ebase + tl.eoff, lds);
         wave_sync();
     }
 }

@@ -23,6 +23,7 @@ struct LaunchPhase1 {
     int D;                 // n + 1
     void* Eout;            // count * 2 * (D + 1) complex (double2, or float2 when fp32)
     int fp32;              // La Budde in complex FP32
+    const int4* lbmap;     // La Budde lane maps of every (team width, D) (lb_fill_table)
 };
 
 // Phase 2: one lane per subset; signed terms, compensated block partials.
@@ -68,12 +69,17 @@ struct SeriesBlock {
 // same (MR, MC) as subsets of size s_rep and the same La Budde team variant;
 // D_max sizes the LDS.
 hipError_t launch_charpoly_batch(int layout, int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles,
-                                 int ntiles, const BatchItem* items, const uint64_t* binom, unsigned* counter,
-                                 void* Ebase, int grid, hipStream_t st);
+                                 int ntiles, const BatchItem* items, const uint64_t* binom, const int4* lbmap,
+                                 unsigned* counter, void* Ebase, int grid, hipStream_t st);
 // Kernel instance id (layout, MR, MC) of subsets of size s under `layout`.
 int charpoly_instance(int layout, int s);
-// La Budde team variant (0, 1, 2) of an n-pair loop hafnian under `layout`.
+// La Budde team variant (0: teams of P Q lanes, 1: one team of 64 lanes) of an
+// n-pair loop hafnian under `layout`.
 int charpoly_variant(int layout, int n);
+// La Budde lane maps for team widths 16, 32, 64 and D = 0..kMaxPairs+1:
+// kLbTableEntries int4 (d, g, first k, last k) per team lane, d = -1 idle.
+constexpr int kLbTableEntries = 3 * (kMaxPairs + 2) * 64;
+void lb_fill_table(int4* out);
 hipError_t launch_series_batch(int n, int fp32, const SeriesBlock* blocks, int nblocks, const BatchTile* tiles,
                                const BatchItem* items, const void* Ebase, int per_thread, double* partials,
                                hipStream_t st);

@@ -401,13 +401,13 @@ bool charpoly_layout_ok(int m, int layout) {
 int charpoly_default_layout(int m) { return m <= 16 ? kLayout44 : (m <= 32 ? kLayout84 : kLayout88); }
 
 hipError_t launch_charpoly_batch_l44(int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
-                                     const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
+                                     const BatchItem* items, const uint64_t* binom, const int4* lbmap, unsigned* counter, void* Ebase,
                                      int grid, hipStream_t st);
 hipError_t launch_charpoly_batch_l84(int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
-                                     const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
+                                     const BatchItem* items, const uint64_t* binom, const int4* lbmap, unsigned* counter, void* Ebase,
                                      int grid, hipStream_t st);
 hipError_t launch_charpoly_batch_l88(int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
-                                     const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
+                                     const BatchItem* items, const uint64_t* binom, const int4* lbmap, unsigned* counter, void* Ebase,
                                      int grid, hipStream_t st);
 
 int charpoly_instance(int layout, int s) {
@@ -424,18 +424,64 @@ int charpoly_variant(int layout, int n) {
     return lb_variant(G, n + 1);
 }
 
+// Lane map of a La Budde team of T lanes carrying coefficients 0..D.
+// Coefficient d >= 2 has d - 1 terms; it gets g_d = 2^ceil(log2(ceil((d-1)/CH)))
+// lanes (capped at 4) with CH the smallest chunk for which all groups fit in
+// T lanes, each lane taking a contiguous run of about (d-1)/g_d terms.  Groups
+// are laid out from the largest d down, so team lane 0 leads the largest group.
+static void lb_fill_one(int T, int D, int4* out) {
+    auto p2 = [](int x) { int p = 1; while (p < x) p *= 2; return p; };
+    int g[kLbMaxD] = {0};
+    bool fit = false;
+    for (int ch = 1; ch <= D && !fit; ++ch) {
+        int tot = 0;
+        bool capped = true;
+        for (int d = 0; d <= D; ++d) {
+            g[d] = (d < 2) ? 1 : p2((d - 1 + ch - 1) / ch);
+            capped = capped && g[d] <= 4;
+            tot += g[d];
+        }
+        fit = capped && tot <= T;
+    }
+    if (!fit)
+        for (int d = 0; d <= D; ++d) g[d] = 1;  // one lane per coefficient (D + 1 <= T)
+    for (int l = 0; l < 64; ++l) out[l] = make_int4(-1, 1, 1, 0);
+    int start = 0;
+    for (int d = D; d >= 0; --d) {
+        const int cs = (d >= 2) ? (d - 1 + g[d] - 1) / g[d] : 0;
+        for (int c = 0; c < g[d]; ++c) {
+            const int klo = 1 + c * cs;
+            const int khi = (d >= 2) ? std::min(d - 1, (c + 1) * cs) : 0;
+            out[start + c] = make_int4(d, g[d], klo, khi);
+        }
+        start += g[d];
+    }
+}
+
+void lb_fill_table(int4* out) {
+    const int teams[3] = {16, 32, 64};
+    for (int ti = 0; ti < 3; ++ti)
+        for (int D = 0; D < kLbMaxD; ++D) {
+            int4* o = out + lb_table_offset(teams[ti], D);
+            if (D + 1 <= teams[ti]) {
+                lb_fill_one(teams[ti], D, o);
+            } else {
+                for (int l = 0; l < 64; ++l) o[l] = make_int4(-1, 1, 1, 0);
+            }
+        }
+}
+
 hipError_t launch_charpoly_batch(int layout, int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles,
-                                 int ntiles,
-                                 const BatchItem* items, const uint64_t* binom, unsigned* counter, void* Ebase,
-                                 int grid, hipStream_t st) {
+                                 int ntiles, const BatchItem* items, const uint64_t* binom, const int4* lbmap,
+                                 unsigned* counter, void* Ebase, int grid, hipStream_t st) {
     if (!charpoly_layout_ok(2 * s_rep, layout)) return hipErrorInvalidValue;
     switch (layout) {
         case kLayout44:
-            return launch_charpoly_batch_l44(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
+            return launch_charpoly_batch_l44(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
         case kLayout84:
-            return launch_charpoly_batch_l84(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
+            return launch_charpoly_batch_l84(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
         default:
-            return launch_charpoly_batch_l88(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, counter, Ebase, grid, st);
+            return launch_charpoly_batch_l88(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
     }
 }
 
