@@ -28,7 +28,12 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU (vect
 # figures are in profiles/charpoly_n50_traffic.md.  Valid only for the kernel
 # sources hashed here: any change to them reports null until re-measured.
 TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_amd/csrc/charpoly_l88.hip")
-TRAFFIC = None  # {"sha256": ..., "kernel": ..., "fetch_bytes": ..., "write_bytes": ..., "subsets": ...}
+TRAFFIC = {
+    "sha256": "aead400b108d5cca35efcaf39a25082146c438237d2eb732f66e2a4a7cdf75c8",
+    "kernel": "charpoly_kernel<8, 8, 4, 4, double2, 64>",
+    "fetch_bytes": 821658,      # 401.2 KiB FETCH_SIZE x 2.0
+    "write_bytes": 219213414,   # 214075.6 KiB WRITE_SIZE x 1.0
+}
 
 
 def sources_sha256():
