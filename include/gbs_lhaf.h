@@ -125,6 +125,20 @@ gbs_status gbs_probability(const gbs_z *Q, const gbs_z *alpha, const int32_t *pa
                            int32_t M, gbs_precision prec, double *p_out, gbs_z *lhaf_out,
                            gbs_diag *diag);
 
+/* Photon-number probability of a general (mixed) Gaussian state, Eq. (11):
+ *   p(S) = p(vac) lhaf(filldiag(A_S, gamma_S)) / prod_i s_i!,   A = X (I - Q^-1) (Eq. (4)),
+ * where A_S repeats rows/columns i and i + M s_i times (a 2N x 2N matrix for N photons,
+ * so N <= GBS_MAX_DIM / 2) and the loop weight of index k is entry X(k) of Q^-1 alpha
+ * (X swaps the two halves: the weights that pair with each block of A; for a pure state
+ * this reduces to Eq. (12)).  Q: 2M x 2M Hermitian positive definite of the form
+ * [[K, L], [conj(L), conj(K)]] (GBS_E_ARG otherwise); alpha: 2M of the form [a; conj(a)]
+ * or NULL (no displacement); pattern: M counts >= 0 (GBS_E_TOO_LARGE above 32 photons).
+ * p_out receives the real part (the loop hafnian of a valid state is real and >= 0;
+ * lhaf_out, nullable, returns it unrounded).  Host pointers; synchronous. */
+gbs_status gbs_probability_mixed(const gbs_z *Q, const gbs_z *alpha, const int32_t *pattern,
+                                 int32_t M, gbs_precision prec, double *p_out, gbs_z *lhaf_out,
+                                 gbs_diag *diag);
+
 /* Signed subset terms t_S of the power-trace sum for an explicit list of pair
  * subsets (bit i of masks[j] set = pair (i, i+n) kept).  A: N x N, its diagonal
  * holds the loop weights.  terms_out[j] receives t_S; sum over all 2^n masks

@@ -219,6 +219,55 @@ def probability(Q, alpha_vec, pattern, prec="ld", lhaf_fn=None):
     return p_vac * abs(lh) ** 2 / fact, lh
 
 
+def mixed_state_params(Q, alpha_vec=None):
+    """(A, gamma, p_vac) of a general (mixed) Gaussian state:
+      A = X (I - Q^-1)                                      Eq. (4), 2M x 2M
+      gamma = X Q^-1 alpha: entry k is the loop weight of index k of A (the
+              half of Q^-1 alpha that pairs with each block, as in reading R1;
+              for a pure state its first half is the pure-state gamma)
+      p(vac) = exp(-alpha^H Q^-1 alpha / 2) / sqrt(det Q)   Eq. (10)"""
+    Q = np.asarray(Q, dtype=np.complex128)
+    M2 = Q.shape[0]
+    M = M2 // 2
+    al = np.zeros(M2, dtype=np.complex128) if alpha_vec is None else np.asarray(alpha_vec, dtype=np.complex128)
+    Qinv = np.linalg.inv(Q)
+    X = np.block([[np.zeros((M, M)), np.eye(M)], [np.eye(M), np.zeros((M, M))]])
+    A = X @ (np.eye(M2) - Qinv)
+    gamma = X @ (Qinv @ al)
+    detQ = np.linalg.det(Q)
+    quad = np.vdot(al, Qinv @ al)
+    p_vac = float(np.exp(-0.5 * quad.real) / math.sqrt(detQ.real))
+    return A, gamma, p_vac
+
+
+def expand_mixed(A, gamma, pattern):
+    """filldiag(A_S, gamma_S) of Eq. (11): rows and columns i and i + M of the
+    2M x 2M matrix A repeated s_i times (copies of first-half indices, then of
+    second-half indices), the diagonal replaced by gamma repeated the same way."""
+    M = len(pattern)
+    idx = [i for i, s in enumerate(pattern) for _ in range(int(s))]
+    idx = idx + [i + M for i in idx]
+    As = np.asarray(A, dtype=np.complex128)[np.ix_(idx, idx)].copy()
+    As[np.diag_indices(len(idx))] = np.asarray(gamma, dtype=np.complex128)[idx]
+    return As
+
+
+def probability_mixed(Q, alpha_vec, pattern, prec="ld", gamma_fn=None):
+    """p(S) = p(vac) lhaf(filldiag(A_S, gamma_S)) / prod s_i!   (Eq. (11)).
+    Returns (p, lhaf); p is the real part (the loop hafnian of a valid state is
+    real and non-negative).  gamma_fn(Q, alpha) overrides the loop weights (used
+    by tests of alternative readings)."""
+    A, gamma, p_vac = mixed_state_params(Q, alpha_vec)
+    if gamma_fn is not None:
+        gamma = gamma_fn(Q, alpha_vec)
+    As = expand_mixed(A, gamma, pattern)
+    lh = to_complex(lhaf_pt(As, prec=prec)) if As.shape[0] else 1.0
+    fact = 1
+    for s in pattern:
+        fact *= math.factorial(int(s))
+    return p_vac * complex(lh).real / fact, lh
+
+
 # ---------------------------------------------------------------------------
 # exact references (pins)
 # ---------------------------------------------------------------------------

@@ -22,6 +22,7 @@ from ._lib import (  # noqa: F401
     max_dim,
     pack,
     probability,
+    probability_mixed,
     profile_enable,
     profile_read,
     pure_state,

@@ -102,6 +102,9 @@ def lib():
         L.gbs_haf.restype = st
         L.gbs_probability.argtypes = [ZP, ZP, I32P, ctypes.c_int32, ctypes.c_int, DP, ZP, ctypes.POINTER(gbs_diag)]
         L.gbs_probability.restype = st
+        L.gbs_probability_mixed.argtypes = [ZP, ZP, I32P, ctypes.c_int32, ctypes.c_int, DP, ZP,
+                                            ctypes.POINTER(gbs_diag)]
+        L.gbs_probability_mixed.restype = st
         L.gbs_lhaf_terms.argtypes = [ZP, ctypes.c_int32, ctypes.c_int64, U64P, ctypes.c_int64, ctypes.c_int, ZP]
         L.gbs_lhaf_terms.restype = st
         L.gbs_lhaf_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
@@ -221,6 +224,26 @@ def probability(Q, alpha, pattern, prec=GBS_FP64, with_lhaf=False):
     _check(lib().gbs_probability(_zp(Q), _zp(al), pat.ctypes.data_as(I32P), M, prec, ctypes.byref(p),
                                  ctypes.byref(lh), None))
     return (p.value, complex(lh.re, lh.im)) if with_lhaf else p.value
+
+
+def probability_mixed(Q, alpha, pattern, prec=GBS_FP64, with_lhaf=False, with_diag=False):
+    """Eq. (11): p(vac) lhaf(filldiag(A_S, gamma_S)) / prod s_i! for a general
+    Gaussian state (alpha None = no displacement)."""
+    Q = _zarr(Q)
+    al = _zarr(alpha) if alpha is not None else None
+    pat = np.ascontiguousarray(pattern, dtype=np.int32)
+    M = pat.shape[0]
+    p = ctypes.c_double(0)
+    lh = gbs_z()
+    d = gbs_diag()
+    _check(lib().gbs_probability_mixed(_zp(Q), _zp(al), pat.ctypes.data_as(I32P), M, prec, ctypes.byref(p),
+                                       ctypes.byref(lh), ctypes.byref(d)))
+    out = [p.value]
+    if with_lhaf:
+        out.append(complex(lh.re, lh.im))
+    if with_diag:
+        out.append(_diag_dict(d))
+    return out[0] if len(out) == 1 else tuple(out)
 
 
 def lhaf_terms(A, masks, prec=GBS_FP64):

@@ -395,15 +395,40 @@ gbs_status gbs_expand(const gbs_z* B, int32_t M, int64_t ldb, const gbs_z* gamma
     return GBS_OK;
 }
 
-gbs_status gbs_pure_state(const gbs_z* Q, const gbs_z* alpha, int32_t M, gbs_z* B_out, gbs_z* gamma_out,
-                          double* p_vac_out) {
+}  // extern "C"
+
+namespace gbs_host {
+
+// Validated parameters of a Gaussian state from Q = Sigma + I/2 (2M x 2M,
+// Hermitian positive definite) and alpha = [a; conj(a)] (nullable = 0):
+// Q^-1, log det Q and Q^-1 alpha.  With `structured`, Q must also have the
+// form [[K, L], [conj(L), conj(K)]] of a covariance in the (a, a^dagger) basis,
+// so that A = X (I - Q^-1) is symmetric.
+struct GaussParams {
+    int M = 0;
+    std::vector<cplx> Qi;  // 2M x 2M
+    std::vector<cplx> qa;  // Q^-1 alpha
+    std::vector<cplx> al;
+    double logdet = 0.0;
+    cplx quad = 0.0;       // alpha^H Q^-1 alpha
+    // A = X (I - Q^-1): rows of the two halves swapped (Eq. (4))
+    cplx A(int i, int j) const {
+        const int n = 2 * M;
+        const int xi = i < M ? i + M : i - M;
+        return ((xi == j) ? cplx(1.0) : cplx(0.0)) - Qi[xi * n + j];
+    }
+};
+
+gbs_status gauss_params(const gbs_z* Q, const gbs_z* alpha, int32_t M, bool structured, GaussParams& G) {
     if (M < 0) return fail(GBS_E_ARG, "negative M");
-    if (M > 0 && (!Q || !alpha)) return fail(GBS_E_ARG, "null Q or alpha");
+    if (M > 0 && !Q) return fail(GBS_E_ARG, "null Q");
     const int n = 2 * M;
+    G.M = M;
     for (int i = 0; i < n * n; ++i)
         if (!finite_z(Q[i])) return fail(GBS_E_NONFINITE, "non-finite Q entry %d", i);
-    for (int i = 0; i < n; ++i)
-        if (!finite_z(alpha[i])) return fail(GBS_E_NONFINITE, "non-finite alpha entry %d", i);
+    if (alpha)
+        for (int i = 0; i < n; ++i)
+            if (!finite_z(alpha[i])) return fail(GBS_E_NONFINITE, "non-finite alpha entry %d", i);
     double qmax = 0.0;
     for (int i = 0; i < n * n; ++i) qmax = std::max(qmax, std::hypot(Q[i].re, Q[i].im));
     for (int i = 0; i < n; ++i)
@@ -412,18 +437,31 @@ gbs_status gbs_pure_state(const gbs_z* Q, const gbs_z* alpha, int32_t M, gbs_z* 
             if (std::hypot(a.re - b.re, a.im + b.im) > 1e-12 * std::max(1.0, qmax))
                 return fail(GBS_E_NOT_PD, "Q is not Hermitian at (%d, %d)", i, j);
         }
-    double amax = 0.0;
-    for (int i = 0; i < n; ++i) amax = std::max(amax, std::hypot(alpha[i].re, alpha[i].im));
-    for (int i = 0; i < M; ++i) {
-        const gbs_z a = alpha[i], b = alpha[M + i];
-        if (std::hypot(a.re - b.re, a.im + b.im) > 1e-12 * std::max(1.0, amax))
-            return fail(GBS_E_ARG, "alpha is not of the form [a; conj(a)] at mode %d", i);
+    if (structured)
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < n; ++j) {
+                // Q[i + M][j'] = conj(Q[i][j]) with j' the partner of j
+                const int jp = j < M ? j + M : j - M;
+                const gbs_z a = Q[i * n + j], b = Q[(i + M) * n + jp];
+                if (std::hypot(a.re - b.re, a.im + b.im) > 1e-12 * std::max(1.0, qmax))
+                    return fail(GBS_E_ARG, "Q lacks the [[K, L], [conj(L), conj(K)]] form at (%d, %d)", i, j);
+            }
+    G.al.assign(n, 0.0);
+    if (alpha) {
+        double amax = 0.0;
+        for (int i = 0; i < n; ++i) amax = std::max(amax, std::hypot(alpha[i].re, alpha[i].im));
+        for (int i = 0; i < M; ++i) {
+            const gbs_z a = alpha[i], b = alpha[M + i];
+            if (std::hypot(a.re - b.re, a.im + b.im) > 1e-12 * std::max(1.0, amax))
+                return fail(GBS_E_ARG, "alpha is not of the form [a; conj(a)] at mode %d", i);
+        }
+        for (int i = 0; i < n; ++i) G.al[i] = cplx(alpha[i].re, alpha[i].im);
     }
     std::vector<cplx> L(n * n);
     for (int i = 0; i < n * n; ++i) L[i] = cplx(Q[i].re, Q[i].im);
     if (!cholesky(L, n)) return fail(GBS_E_NOT_PD, "Q is not positive definite");
     // Q^-1 = L^-H L^-1, column by column
-    std::vector<cplx> Qi(n * n);
+    G.Qi.assign(n * n, 0.0);
     std::vector<cplx> col(n);
     for (int j = 0; j < n; ++j) {
         for (int i = 0; i < n; ++i) {
@@ -436,42 +474,102 @@ gbs_status gbs_pure_state(const gbs_z* Q, const gbs_z* alpha, int32_t M, gbs_z* 
             for (int k = i + 1; k < n; ++k) s -= std::conj(L[k * n + i]) * col[k];
             col[i] = s / L[i * n + i].real();
         }
-        for (int i = 0; i < n; ++i) Qi[i * n + j] = col[i];
+        for (int i = 0; i < n; ++i) G.Qi[i * n + j] = col[i];
     }
-    double logdet = 0.0;
-    for (int i = 0; i < n; ++i) logdet += 2.0 * std::log(L[i * n + i].real());
-    // A = X (I - Q^-1): rows of the two halves swapped
-    auto Aat = [&](int i, int j) {
-        const int xi = i < M ? i + M : i - M;
-        return ((xi == j) ? cplx(1.0) : cplx(0.0)) - Qi[xi * n + j];
-    };
-    double anorm = 0.0, offb = 0.0, diffb = 0.0;
+    G.logdet = 0.0;
+    for (int i = 0; i < n; ++i) G.logdet += 2.0 * std::log(L[i * n + i].real());
+    G.qa.assign(n, 0.0);
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) anorm = std::max(anorm, std::abs(Aat(i, j)));
+        for (int j = 0; j < n; ++j) G.qa[i] += G.Qi[i * n + j] * G.al[j];
+    G.quad = 0.0;
+    for (int i = 0; i < n; ++i) G.quad += std::conj(G.al[i]) * G.qa[i];
+    return GBS_OK;
+}
+
+double lfactorial_sum(const int32_t* pattern, int M) {
+    double lf = 0.0;
+    for (int i = 0; i < M; ++i) lf += std::lgamma((double)pattern[i] + 1.0);
+    return lf;
+}
+
+}  // namespace gbs_host
+
+extern "C" {
+
+gbs_status gbs_pure_state(const gbs_z* Q, const gbs_z* alpha, int32_t M, gbs_z* B_out, gbs_z* gamma_out,
+                          double* p_vac_out) {
+    if (M > 0 && (!Q || !alpha)) return fail(GBS_E_ARG, "null Q or alpha");
+    GaussParams G;
+    gbs_status st = gauss_params(Q, alpha, M, false, G);
+    if (st != GBS_OK) return st;
+    double anorm = 0.0, offb = 0.0, diffb = 0.0;
+    const int n = 2 * M;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) anorm = std::max(anorm, std::abs(G.A(i, j)));
     for (int i = 0; i < M; ++i)
         for (int j = 0; j < M; ++j) {
-            offb = std::max(offb, std::abs(Aat(i, M + j)));
-            offb = std::max(offb, std::abs(Aat(M + i, j)));
-            diffb = std::max(diffb, std::abs(Aat(M + i, M + j) - std::conj(Aat(i, j))));
+            offb = std::max(offb, std::abs(G.A(i, M + j)));
+            offb = std::max(offb, std::abs(G.A(M + i, j)));
+            diffb = std::max(diffb, std::abs(G.A(M + i, M + j) - std::conj(G.A(i, j))));
         }
     if (offb > 1e-10 * std::max(1.0, anorm) || diffb > 1e-10 * std::max(1.0, anorm))
         return fail(GBS_E_NOT_PURE, "A = X(I - Q^-1) is not B (+) conj(B) (off-block %.3g, mismatch %.3g)", offb, diffb);
-    std::vector<cplx> al(n);
-    for (int i = 0; i < n; ++i) al[i] = cplx(alpha[i].re, alpha[i].im);
-    std::vector<cplx> qa(n, 0.0);
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) qa[i] += Qi[i * n + j] * al[j];
-    cplx quad = 0.0;
-    for (int i = 0; i < n; ++i) quad += std::conj(al[i]) * qa[i];
     if (B_out)
         for (int i = 0; i < M; ++i)
             for (int j = 0; j < M; ++j) {
-                const cplx b = Aat(i, j);
+                const cplx b = G.A(i, j);
                 B_out[i * M + j] = gbs_z{b.real(), b.imag()};
             }
+    // the loop weights pairing with B are the second half of Q^-1 alpha
     if (gamma_out)
-        for (int i = 0; i < M; ++i) gamma_out[i] = gbs_z{qa[M + i].real(), qa[M + i].imag()};
-    if (p_vac_out) *p_vac_out = std::exp(-0.5 * quad.real() - 0.5 * logdet);
+        for (int i = 0; i < M; ++i) gamma_out[i] = gbs_z{G.qa[M + i].real(), G.qa[M + i].imag()};
+    if (p_vac_out) *p_vac_out = std::exp(-0.5 * G.quad.real() - 0.5 * G.logdet);
+    return GBS_OK;
+}
+
+gbs_status gbs_probability_mixed(const gbs_z* Q, const gbs_z* alpha, const int32_t* pattern, int32_t M,
+                                 gbs_precision prec, double* p_out, gbs_z* lhaf_out, gbs_diag* diag) {
+    if (!p_out || (M > 0 && !pattern)) return fail(GBS_E_ARG, "null output or pattern");
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    int64_t photons = 0;
+    for (int i = 0; i < M; ++i) {
+        if (pattern[i] < 0) return fail(GBS_E_ARG, "negative photon number at mode %d", i);
+        photons += pattern[i];
+    }
+    if (2 * photons > GBS_MAX_DIM)
+        return fail(GBS_E_TOO_LARGE, "%lld photons need a %lld x %lld loop hafnian (max %d)", (long long)photons,
+                    (long long)(2 * photons), (long long)(2 * photons), GBS_MAX_DIM);
+    GaussParams G;
+    gbs_status st = gauss_params(Q, alpha, M, true, G);
+    if (st != GBS_OK) return st;
+    // rows/columns i and i + M repeated s_i times: first-half copies, then second-half copies
+    std::vector<int> idx;
+    for (int half = 0; half < 2; ++half)
+        for (int i = 0; i < M; ++i)
+            for (int c = 0; c < pattern[i]; ++c) idx.push_back(i + half * M);
+    const int N = (int)idx.size();
+    std::vector<gbs_z> As((size_t)N * N);
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
+            cplx v;
+            if (a == b) {
+                // loop weight of index k: the entry of Q^-1 alpha of its partner index (X Q^-1 alpha)
+                const int k = idx[a];
+                v = G.qa[k < M ? k + M : k - M];
+            } else {
+                v = G.A(idx[a], idx[b]);
+            }
+            As[(size_t)a * N + b] = gbs_z{v.real(), v.imag()};
+        }
+    gbs_z lh{1.0, 0.0};
+    {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        st = lhaf_host_matrix(As.data(), N, &lh, diag, prec == GBS_FP32_COMP);
+    }
+    if (st != GBS_OK) return st;
+    const double scale = std::exp(-0.5 * G.quad.real() - 0.5 * G.logdet - lfactorial_sum(pattern, M));
+    *p_out = scale * lh.re;
+    if (lhaf_out) *lhaf_out = lh;
     return GBS_OK;
 }
 
@@ -524,9 +622,7 @@ gbs_status gbs_probability(const gbs_z* Q, const gbs_z* alpha, const int32_t* pa
         st = lhaf_host_matrix(Aexp.data(), N, &lh, diag, prec == GBS_FP32_COMP);
     }
     if (st != GBS_OK) return st;
-    double lfact = 0.0;
-    for (int i = 0; i < M; ++i) lfact += std::lgamma((double)pattern[i] + 1.0);
-    *p_out = pvac * (lh.re * lh.re + lh.im * lh.im) * std::exp(-lfact);
+    *p_out = pvac * (lh.re * lh.re + lh.im * lh.im) * std::exp(-lfactorial_sum(pattern, M));
     if (lhaf_out) *lhaf_out = lh;
     return GBS_OK;
 }

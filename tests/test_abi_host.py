@@ -128,3 +128,21 @@ def test_yardstick_flops_formula():
         ref = sum(comb(n, s) * ((44 / 3) * (2 * s) ** 3 + 8 * min(n - 1, 2 * s - 1) * (2 * s) ** 2) for s in range(1, n + 1))
         assert gbs.yardstick_flops(N) == pytest.approx(ref, rel=1e-12)
     assert gbs.yardstick_flops(50) == pytest.approx(1.260e13, rel=1e-3)
+
+
+def test_mixed_probability_validation():
+    """Argument errors of gbs_probability_mixed are reported before any device work."""
+    st = workloads.pure_state(2, 0.5, 0.2, seed=9)
+    Q = st["Q"] + np.diag([0.1, 0.1, 0.1, 0.1])
+    _expect(-1, gbs.probability_mixed, Q, st["alpha_vec"], [1, -1])
+    _expect(-4, gbs.probability_mixed, Q, st["alpha_vec"], [20, 13])  # 66 x 66 loop hafnian
+    Qbad = Q.copy()
+    Qbad[0, 1] += 0.2
+    Qbad[1, 0] += 0.2  # Hermitian, but not of the form [[K, L], [conj(L), conj(K)]]
+    _expect(-1, gbs.probability_mixed, Qbad, st["alpha_vec"], [1, 1])
+    Qh = Q.copy()
+    Qh[0, 1] += 0.3j  # not Hermitian
+    _expect(-6, gbs.probability_mixed, Qh, st["alpha_vec"], [1, 1])
+    al = st["alpha_vec"].copy()
+    al[2] = 3.0
+    _expect(-1, gbs.probability_mixed, Q, al, [1, 1])
