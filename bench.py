@@ -200,6 +200,130 @@ def bench_batch(args, gbs):
     print(json.dumps(result), flush=True)
 
 
+FIG1_PAPER_TVD_PCT = {  # Fig. 1 of the paper: modes -> (expected TVD %, TVD % of the algorithm), 200000 samples
+    1: (0.0673495237048602, 0.0647525723905912), 2: (0.160458530772439, 0.156253393597565),
+    3: (0.326807192070019, 0.330725502822026), 4: (0.574908610108614, 0.560088803231853),
+    5: (0.956263734732863, 0.945682615697726), 6: (1.60448581724988, 1.60403702590985),
+}
+
+
+def sampler_state(M, seed):
+    """Fig. 1 setting: squeezing r = 0.5 in every mode into a Haar-random interferometer, no displacement."""
+    from paper_2010_15595_amd import workloads
+
+    return workloads.pure_state(M, 0.5, 0.0, seed=seed)
+
+
+def bench_sampler(args, gbs):
+    """One step = one gbs_sample_pure call drawing args.samples samples of the
+    6-mode Fig. 1 state (r = 0.5, Haar interferometer, cutoff 6)."""
+    import numpy as np
+
+    M, cutoff = args.sampler_modes, 6
+    st = sampler_state(M, seed=2024)
+    rng = np.random.default_rng(7)
+    n = args.samples
+    z = rng.standard_normal((n, 2 * (M - 1)))
+    u = rng.random((n, M))
+    prec = gbs.GBS_FP64 if args.precision == "fp64" else gbs.GBS_FP32_COMP
+    gbs.init(0)
+    for _ in range(args.warmup):
+        ref = gbs.sample_pure(st["Q"], st["alpha_vec"], cutoff, z, u, prec=prec)
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        s, info = gbs.sample_pure(st["Q"], st["alpha_vec"], cutoff, z, u, prec=prec, with_info=True)
+        infos.append(info)
+    sec = time.perf_counter() - t0
+    if args.warmup > 0 and not np.array_equal(s, ref):
+        log("WARNING: samples changed between identical calls")
+    info = infos[-1]
+    rate = args.steps * n / sec
+    log(f"{args.steps} x {n} samples in {sec:.2f} s: {rate:.1f} samples/s, "
+        f"{args.steps * info['loop_hafnians'] / sec:.3e} lhaf/s; info {info}")
+    result = {
+        "metric": "samples/s of the conditional sampling chain (Fig. 1 setting)",
+        "value": rate,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if args.precision == "fp64" else "c128 Hessenberg + c64 La Budde/series (compensated)",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{n} samples per step of a {M}-mode pure state: r = 0.5 squeezing in every mode into a "
+                        f"Haar-random interferometer, cutoff {cutoff}; host random numbers, host samples out "
+                        "(wall clock of the synchronous call, PCIe included)",
+            "samples_per_step": n,
+            "modes": M,
+            "cutoff": cutoff,
+        },
+        "loop_hafnians_per_s": args.steps * info["loop_hafnians"] / sec,
+        "subset_terms_per_step": info["subset_terms"],
+        "max_dim": info["max_dim"],
+        "host_setup_ms": info["setup_ms"],
+        "mean_photons": float(s.sum(axis=1).mean()),
+    }
+    print(json.dumps(result), flush=True)
+
+
+def fig1_tvd(args, gbs):
+    """Fig. 1 of the paper: for 1..6 modes and 10 Haar-random unitaries, the
+    total variation distance between args.samples samples of the chain and the
+    exact distribution of patterns with s_i <= 6, beside the TVD of as many
+    samples drawn from the exact distribution itself.  Exact probabilities of
+    all patterns with at most args.tvd_max_photons photons come from one batch
+    plan of loop hafnians (the rest weigh below the statistical resolution)."""
+    import itertools
+
+    import numpy as np
+
+    cutoff, n = 6, args.samples
+    gbs.init(0)
+    rows = {}
+    for M in range(1, args.sampler_modes + 1):
+        tv, ex = [], []
+        for rep in range(args.tvd_unitaries):
+            st = sampler_state(M, seed=1000 * M + rep)
+            B, gamma, pvac = gbs.pure_state(st["Q"], st["alpha_vec"])
+            pats = [p for p in itertools.product(range(cutoff + 1), repeat=M) if sum(p) <= args.tvd_max_photons]
+            mats = [gbs.expand(B, gamma, p) for p in pats]
+            plan = gbs.BatchPlan([a.shape[0] for a in mats])
+            import torch
+
+            dev = torch.device("cuda:0")
+            packed = torch.from_numpy(gbs.pack(mats)).to(dev)
+            out = torch.zeros(len(mats), dtype=torch.complex128, device=dev)
+            plan.run(packed, out, None, torch.cuda.current_stream(dev))
+            torch.cuda.synchronize()
+            plan.close()
+            lh = out.cpu().numpy()
+            fact = np.array([np.prod([math.factorial(x) for x in p]) for p in pats], dtype=float)
+            prob = pvac * np.abs(lh) ** 2 / fact
+            prob = prob / prob.sum()
+            rng = np.random.default_rng(rep + 17 * M)
+            s = gbs.sample_pure(st["Q"], st["alpha_vec"], cutoff, rng.standard_normal((n, 2 * (M - 1))),
+                                rng.random((n, M)))
+            base = (cutoff + 1) ** np.arange(M - 1, -1, -1)
+            codes = s @ base
+            emp = np.bincount(codes, minlength=(cutoff + 1) ** M) / n
+            ref = np.zeros_like(emp)
+            ref[np.array(pats) @ base] = prob
+            tv.append(50.0 * np.abs(emp - ref).sum())
+            ex.append(50.0 * np.abs(rng.multinomial(n, ref) / n - ref).sum())
+        rows[M] = {"tvd_pct": float(np.mean(tv)), "tvd_pct_std": float(np.std(tv)),
+                   "expected_tvd_pct": float(np.mean(ex)), "expected_tvd_pct_std": float(np.std(ex)),
+                   "paper_expected_pct": FIG1_PAPER_TVD_PCT[M][0], "paper_algorithm_pct": FIG1_PAPER_TVD_PCT[M][1]}
+        log(f"M={M}: {rows[M]}")
+    print(json.dumps({"metric": "total variation distance % (Fig. 1)", "samples": n, "cutoff": cutoff,
+                      "unitaries": args.tvd_unitaries, "max_photons_in_reference": args.tvd_max_photons,
+                      "modes": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,9 +340,14 @@ def main():
                     help="print the hash of the kernel sources the traffic figures are tied to")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["n50", "batch"], default="n50",
+    ap.add_argument("--workload", choices=["n50", "batch", "sampler", "tvd"], default="n50",
                     help="batch: 4096 loop hafnians of uneven N in [10, 36] from one 100-mode state, "
-                         "one captured graph of persistent launches per step")
+                         "one captured graph of persistent launches per step; sampler: samples/s of the "
+                         "conditional sampling chain in the Fig. 1 setting; tvd: the Fig. 1 experiment")
+    ap.add_argument("--samples", type=int, default=200000, help="sampler / tvd: samples per step / per unitary")
+    ap.add_argument("--sampler-modes", type=int, default=6)
+    ap.add_argument("--tvd-unitaries", type=int, default=10)
+    ap.add_argument("--tvd-max-photons", type=int, default=14)
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--no-plain", action="store_true", help="batch: skip timing the items one at a time")
     args = ap.parse_args()
@@ -256,6 +385,10 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args, gbs)
+    if args.workload == "sampler":
+        return bench_sampler(args, gbs)
+    if args.workload == "tvd":
+        return fig1_tvd(args, gbs)
 
     N = args.N
     st = workload(N)

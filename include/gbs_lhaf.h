@@ -197,6 +197,42 @@ gbs_status gbs_batch_run(gbs_plan *plan, const gbs_z *mats_dev, gbs_z *out_dev, 
                          void *stream);
 void gbs_batch_plan_destroy(gbs_plan *plan);
 
+/* ---- conditional sampling chain ------------------------------------------ */
+
+typedef struct {
+    int64_t loop_hafnians; /* loop hafnians evaluated: nsamples * M * (cutoff + 1)     */
+    int64_t subset_terms;  /* sum over them of 2^n                                      */
+    int32_t max_dim;       /* largest loop-hafnian dimension met                        */
+    int32_t groups;        /* lockstep groups of samples (up to 8192 samples each)      */
+    double setup_ms;       /* host conditioning of the covariance, once per call        */
+    double total_ms;       /* wall time of the call                                     */
+} gbs_sample_info;
+
+/* Photon-number samples of a pure Gaussian state by the algorithm of Sec. III:
+ * heterodyne outcomes beta_2..beta_M are drawn from the Husimi distribution
+ * (mean and augmented covariance: alpha and Q of those modes); then for
+ * k = 1..M the photon number of mode k is drawn from the probabilities
+ * (Eq. (12)) of the patterns (s_1, .., s_{k-1}, j), j = 0..cutoff, of the pure
+ * state of modes 1..k conditioned on beta_{k+1}..beta_M (Gaussian conditioning,
+ * Sec. II), normalised over j.
+ * Q (2M x 2M) and alpha (2M) as for gbs_probability; M <= 128.  All randomness
+ * is passed in, row-major per sample:
+ *   normals  (nsamples x 2(M-1)): x = m + L z with z these normals, L the lower
+ *            Cholesky factor and m the mean of x = (Re beta_2..Re beta_M,
+ *            Im beta_2..Im beta_M); NULL allowed when M = 1;
+ *   uniforms (nsamples x M) in [0, 1): s_k = #{j : cdf_j <= u_k}, at most
+ *            cutoff, with cdf_j the running sum of the normalised probabilities.
+ * samples_out (nsamples x M) receives the patterns; probs_out (nullable,
+ * nsamples x M x (cutoff + 1)) the normalised conditional probabilities each
+ * draw used.  Every loop hafnian runs on the GPU; GBS_E_TOO_LARGE when a
+ * sample's photons so far plus cutoff exceed GBS_MAX_DIM (never when
+ * M * cutoff <= GBS_MAX_DIM), GBS_E_NONFINITE when a step's probabilities are
+ * not finite or all zero.  Host pointers; synchronous.  info may be NULL. */
+gbs_status gbs_sample_pure(const gbs_z *Q, const gbs_z *alpha, int32_t M, int32_t cutoff,
+                           const double *normals, const double *uniforms, int32_t nsamples,
+                           gbs_precision prec, int32_t *samples_out, double *probs_out,
+                           gbs_sample_info *info);
+
 /* ---- kernel layout selection and autotuning ------------------------------ */
 
 /* Lane grid of the per-subset kernel (rows x columns of lanes per subset). */

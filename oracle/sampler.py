@@ -56,23 +56,25 @@ def conditional_state(Q, alpha_vec, A, B, beta_B):
     return S_A + 0.5 * np.eye(len(ia)), a_A
 
 
-def sample_chain(Q, alpha_vec, cutoff, normals, uniforms, prec="d"):
+def sample_chain(Q, alpha_vec, cutoff, normals, uniforms, prec="d", return_probs=False):
     """One sample of the Algorithm of Sec. III for a pure state: heterodyne
     outcomes for modes 2..M, then for k = 1..M the conditional pure state of
     modes 1..k, the probabilities of s_k = 0..cutoff (Eq. (12)) and an
-    inverse-CDF draw.  Returns the photon pattern (M ints)."""
+    inverse-CDF draw.  Returns the photon pattern (M ints), and with
+    return_probs also the (M, cutoff + 1) normalised probabilities drawn from."""
     M = np.asarray(Q).shape[0] // 2
     beta = heterodyne_sample(Q, alpha_vec, range(1, M), normals) if M > 1 else np.zeros(0, complex)
-    s = []
+    s, probs = [], []
     for k in range(1, M + 1):
         A = list(range(k))
         B = list(range(k, M))
         QA, aA = conditional_state(Q, alpha_vec, A, B, beta[k - 1:])
         p = np.array([probability(QA, aA, s + [j], prec=prec)[0] for j in range(cutoff + 1)])
-        cdf = np.cumsum(p / p.sum())
+        probs.append(p / p.sum())
+        cdf = np.cumsum(probs[-1])
         j = int(np.searchsorted(cdf, uniforms[k - 1], side="right"))
         s.append(min(j, cutoff))
-    return s
+    return (s, np.array(probs)) if return_probs else s
 
 
 def exact_distribution(Q, alpha_vec, cutoff, prec="d"):

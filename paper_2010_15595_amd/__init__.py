@@ -2,7 +2,8 @@
 
 The loop hafnian of a complex symmetric matrix by the power-trace subset sum
 (Quesada et al., arXiv:2010.15595, Sec. IV) and the pure-state photon-number
-probability of Sec. II, Eq. (12), computed by hand-written HIP kernels behind
+probability of Sec. II, Eq. (12), the mixed-state probability of Eq. (11)
+and the conditional sampling chain of Sec. III, computed by hand-written HIP kernels behind
 the C ABI of include/gbs_lhaf.h.  This package is the thin Python binding.
 """
 from ._lib import (  # noqa: F401
@@ -26,6 +27,7 @@ from ._lib import (  # noqa: F401
     profile_enable,
     profile_read,
     pure_state,
+    sample_pure,
     selftest,
     set_layout,
     yardstick_flops,

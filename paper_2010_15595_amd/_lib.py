@@ -50,6 +50,11 @@ class gbs_batch_info(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_int64), ("yardstick_flops", ctypes.c_double), ("tune_ms", ctypes.c_double)]
 
 
+class gbs_sample_info(ctypes.Structure):
+    _fields_ = [("loop_hafnians", ctypes.c_int64), ("subset_terms", ctypes.c_int64), ("max_dim", ctypes.c_int32),
+                ("groups", ctypes.c_int32), ("setup_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
 class gbs_profile(ctypes.Structure):
     _fields_ = [("charpoly_ms", ctypes.c_double), ("series_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double),
                 ("charpoly_launches", ctypes.c_int64), ("series_launches", ctypes.c_int64),
@@ -105,6 +110,9 @@ def lib():
         L.gbs_probability_mixed.argtypes = [ZP, ZP, I32P, ctypes.c_int32, ctypes.c_int, DP, ZP,
                                             ctypes.POINTER(gbs_diag)]
         L.gbs_probability_mixed.restype = st
+        L.gbs_sample_pure.argtypes = [ZP, ZP, ctypes.c_int32, ctypes.c_int32, DP, DP, ctypes.c_int32, ctypes.c_int,
+                                      I32P, DP, ctypes.POINTER(gbs_sample_info)]
+        L.gbs_sample_pure.restype = st
         L.gbs_lhaf_terms.argtypes = [ZP, ctypes.c_int32, ctypes.c_int64, U64P, ctypes.c_int64, ctypes.c_int, ZP]
         L.gbs_lhaf_terms.restype = st
         L.gbs_lhaf_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
@@ -244,6 +252,33 @@ def probability_mixed(Q, alpha, pattern, prec=GBS_FP64, with_lhaf=False, with_di
     if with_diag:
         out.append(_diag_dict(d))
     return out[0] if len(out) == 1 else tuple(out)
+
+
+def sample_pure(Q, alpha, cutoff, normals, uniforms, prec=GBS_FP64, with_probs=False, with_info=False):
+    """Samples of a pure state by the conditional chain of Sec. III.
+
+    normals: (nsamples, 2 (M - 1)) standard normals of the heterodyne outcomes
+    of modes 2..M; uniforms: (nsamples, M) in [0, 1) for the photon-number
+    draws.  Returns the (nsamples, M) int32 patterns, plus the (nsamples, M,
+    cutoff + 1) normalised conditional probabilities and/or an info dict."""
+    Q = _zarr(Q)
+    al = _zarr(alpha)
+    M = Q.shape[0] // 2
+    u = np.ascontiguousarray(uniforms, dtype=np.float64).reshape(-1, M)
+    ns = u.shape[0]
+    z = np.ascontiguousarray(normals, dtype=np.float64).reshape(ns, 2 * (M - 1))
+    out = np.zeros((ns, M), dtype=np.int32)
+    probs = np.zeros((ns, M, cutoff + 1)) if with_probs else None
+    info = gbs_sample_info()
+    _check(lib().gbs_sample_pure(_zp(Q), _zp(al), M, cutoff, z.ctypes.data_as(DP) if z.size else None,
+                                 u.ctypes.data_as(DP), ns, prec, out.ctypes.data_as(I32P),
+                                 probs.ctypes.data_as(DP) if with_probs else None, ctypes.byref(info)))
+    res = [out]
+    if with_probs:
+        res.append(probs)
+    if with_info:
+        res.append({f: getattr(info, f) for f, _ in gbs_sample_info._fields_})
+    return res[0] if len(res) == 1 else tuple(res)
 
 
 def lhaf_terms(A, masks, prec=GBS_FP64):

@@ -18,7 +18,8 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result",
 ]
-SOURCES = ["charpoly_l88.hip", "charpoly_l84.hip", "charpoly_l44.hip", "lhaf_kernels.hip", "gbs_host.cpp", "gbs_batch.cpp"]
+SOURCES = ["charpoly_l88.hip", "charpoly_l84.hip", "charpoly_l44.hip", "lhaf_kernels.hip", "gbs_host.cpp", "gbs_batch.cpp",
+           "sampler_kernels.hip", "gbs_sampler.cpp"]
 
 
 def _compile(src):

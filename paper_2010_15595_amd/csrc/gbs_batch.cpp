@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <numeric>
 #include <vector>
@@ -30,79 +31,199 @@ namespace {
 
 constexpr int kSeriesPerThread = 8;                   // subsets per lane in the series kernel
 constexpr int kSeriesBlock = 64 * kSeriesPerThread;   // subsets per series block
-constexpr int kBranches = 4;                          // parallel graph branches per round
 constexpr int kPersistentWaves = 256 * 8;             // wavefronts of a persistent launch
-
-struct CharpolyLaunch {
-    int round, layout, s_rep, inst, variant;
-    int tile_begin, ntiles;  // range in the device tile array
-    int counter;
-};
-
-struct SeriesLaunch {
-    int round, n;
-    int block_begin, nblocks;
-};
 
 }  // namespace
 
 struct gbs_plan {
     int device = 0;
-    int count = 0;
-    bool fp32 = false;
-    int64_t tile_subsets = 0;
-    int rounds = 0;
-    int64_t subset_terms = 0;
-    double flops = 0.0;
+    BatchSchedule S;
     double tune_ms = 0.0;
-    int64_t in_elems = 0;
     size_t bytes = 0;
-    int max_n = 0;
-    std::vector<CharpolyLaunch> cp;
-    std::vector<SeriesLaunch> se;
-    int ntiles = 0;
-    // device memory
-    double2* staging = nullptr;   // packed input copy
-    double2* a0 = nullptr;        // per-item A0 blocks
-    double2* dv = nullptr;        // per-item loop weights
-    gbs::BatchItem* items = nullptr;
-    int64_t* in_off = nullptr;
-    int* dims = nullptr;
-    gbs::BatchTile* tiles = nullptr;
-    gbs::SeriesBlock* sblocks = nullptr;
-    int64_t* pbeg = nullptr;
-    double* partials = nullptr;
-    unsigned* counters = nullptr;
-    void* ebuf[2] = {nullptr, nullptr};
-    double2* out = nullptr;
-    double* abs = nullptr;
+    BatchDev d;
+    double2* staging = nullptr;  // packed input copy (the graph reads a fixed address)
     hipStream_t cs = nullptr;
-    hipStream_t br[kBranches] = {};
+    hipStream_t br[kBatchBranches] = {};
     std::vector<hipEvent_t> events;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t t0 = nullptr, t1 = nullptr;
 };
 
-namespace {
+namespace gbs_host {
 
-void plan_free(gbs_plan* p) {
-    if (!p) return;
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    for (hipEvent_t e : p->events) hipEventDestroy(e);
-    if (p->t0) hipEventDestroy(p->t0);
-    if (p->t1) hipEventDestroy(p->t1);
-    for (hipStream_t s : p->br)
-        if (s) hipStreamDestroy(s);
-    if (p->cs) hipStreamDestroy(p->cs);
-    void* bufs[] = {p->staging, p->a0,       p->dv,       p->items,   p->in_off, p->dims,    p->tiles,
-                    p->sblocks, p->pbeg,     p->partials, p->counters, p->ebuf[0], p->ebuf[1], p->out,
-                    p->abs};
-    for (void* b : bufs)
-        if (b) hipFree(b);
-    delete p;
+void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, int64_t tile_subsets,
+                    int64_t round_bytes, BatchSchedule& S) {
+    S = BatchSchedule();
+    S.count = (int)dims.size();
+    S.fp32 = fp32;
+    S.tile_subsets = tile_subsets;
+    S.dims = dims;
+    const int64_t vbytes = fp32 ? (int64_t)sizeof(float2) : (int64_t)sizeof(double2);
+    const int nitems = S.count;
+
+    // items
+    S.in_off.resize(nitems);
+    S.a0_off.resize(nitems);
+    S.d_off.resize(nitems);
+    S.npair.resize(nitems);
+    for (int i = 0; i < nitems; ++i) {
+        const int N = dims[i], Np = N + (N & 1);
+        S.npair[i] = Np / 2;
+        S.in_off[i] = S.in_elems;
+        S.a0_off[i] = S.a0_elems;
+        S.d_off[i] = S.d_elems;
+        S.in_elems += (int64_t)N * N;
+        S.a0_elems += (int64_t)Np * Np;
+        S.d_elems += Np;
+        S.max_n = std::max(S.max_n, Np / 2);
+        S.subset_terms += (int64_t)1 << (Np / 2);
+        S.flops += gbs_yardstick_flops(N);
+    }
+
+    // tiles: (item, s, rank range); series blocks and partial ranges per item
+    struct HostTile {
+        gbs::BatchTile t;
+        int inst, layout, variant;
+        double cost;
+        int round;
+    };
+    std::vector<HostTile> ht;
+    for (int i = 0; i < nitems; ++i) {
+        const int n = S.npair[i];
+        for (int s = 1; s <= n; ++s) {
+            const uint64_t cnt = binom_host(n, s);
+            const int lay = layout_for(c, n, s);
+            for (uint64_t r0 = 0; r0 < cnt; r0 += (uint64_t)tile_subsets) {
+                HostTile h{};
+                h.t.rank0 = r0;
+                h.t.count = std::min<uint64_t>((uint64_t)tile_subsets, cnt - r0);
+                h.t.item = i;
+                h.t.s = s;
+                h.layout = lay;
+                h.variant = gbs::charpoly_variant(lay, n);
+                h.inst = 4 * gbs::charpoly_instance(lay, s) + h.variant;
+                h.cost = subset_flops(n, s) * (double)h.t.count;
+                ht.push_back(h);
+            }
+        }
+    }
+    // partials: per item contiguous, in (item, s, rank) order
+    S.pbeg.assign(nitems + 1, 0);
+    std::vector<int64_t> tile_pidx(ht.size());
+    {
+        int64_t pi = 0;
+        size_t k = 0;
+        for (int i = 0; i < nitems; ++i) {
+            S.pbeg[i] = pi;
+            while (k < ht.size() && ht[k].t.item == i) {
+                tile_pidx[k] = pi;
+                pi += (int64_t)((ht[k].t.count + kSeriesBlock - 1) / kSeriesBlock);
+                ++k;
+            }
+        }
+        S.pbeg[nitems] = pi;
+    }
+    // rounds: tiles in decreasing cost, filled up to round_bytes of coefficients
+    std::vector<size_t> order(ht.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return ht[a].cost > ht[b].cost; });
+    std::vector<int64_t> round_fill;
+    for (size_t k : order) {
+        const int64_t need = (int64_t)ht[k].t.count * 2 * (S.npair[ht[k].t.item] + 2) * vbytes;
+        int r = (int)round_fill.size() - 1;
+        if (r < 0 || round_fill[r] + need > round_bytes) {
+            round_fill.push_back(0);
+            r = (int)round_fill.size() - 1;
+        }
+        ht[k].t.eoff = (uint64_t)(round_fill[r] / vbytes);
+        round_fill[r] += need;
+        ht[k].round = r;
+    }
+    S.rounds = (int)round_fill.size();
+    S.ebuf_bytes = round_fill.empty() ? 16 : *std::max_element(round_fill.begin(), round_fill.end());
+
+    // device tile array: grouped by (round, instance), largest first inside a group
+    std::vector<size_t> dorder(order);
+    std::stable_sort(dorder.begin(), dorder.end(), [&](size_t a, size_t b) {
+        if (ht[a].round != ht[b].round) return ht[a].round < ht[b].round;
+        return ht[a].inst < ht[b].inst;  // stable: cost order kept inside
+    });
+    S.tiles.resize(dorder.size());
+    std::vector<int> pos_of(ht.size());
+    for (size_t q = 0; q < dorder.size(); ++q) {
+        S.tiles[q] = ht[dorder[q]].t;
+        pos_of[dorder[q]] = (int)q;
+    }
+    for (size_t q = 0; q < dorder.size();) {
+        size_t e = q;
+        while (e < dorder.size() && ht[dorder[e]].round == ht[dorder[q]].round &&
+               ht[dorder[e]].inst == ht[dorder[q]].inst)
+            ++e;
+        const HostTile& h = ht[dorder[q]];
+        S.cp.push_back(
+            CharpolyLaunch{h.round, h.layout, h.t.s, h.inst, h.variant, (int)q, (int)(e - q), (int)S.cp.size()});
+        q = e;
+    }
+    // series blocks grouped by (round, n)
+    std::map<std::pair<int, int>, std::vector<gbs::SeriesBlock>> by;
+    for (size_t k = 0; k < ht.size(); ++k) {
+        const int n = S.npair[ht[k].t.item];
+        auto& v = by[{ht[k].round, n}];
+        int64_t pi = tile_pidx[k];
+        for (uint64_t s0 = 0; s0 < ht[k].t.count; s0 += kSeriesBlock)
+            v.push_back(gbs::SeriesBlock{pos_of[k], (int)pi++, s0});
+    }
+    for (auto& kv : by) {
+        S.se.push_back(SeriesLaunch{kv.first.first, kv.first.second, (int)S.sblocks.size(), (int)kv.second.size()});
+        S.sblocks.insert(S.sblocks.end(), kv.second.begin(), kv.second.end());
+    }
 }
+
+gbs_status batch_enqueue(DevCtx* c, const BatchSchedule& S, const BatchDev& d, hipStream_t cs, hipStream_t* br,
+                         const std::function<hipError_t(hipEvent_t*)>& new_event) {
+    const int nitems = S.count;
+    HIP_TRY(gbs::launch_fill_u32(d.counters, (int)std::max<size_t>(1, S.cp.size()), cs));
+    HIP_TRY(gbs::launch_batch_prep(d.mats, d.in_off, d.dims, d.items, nitems, cs));
+    hipEvent_t ev_prep;
+    HIP_TRY(new_event(&ev_prep));
+    HIP_TRY(hipEventRecord(ev_prep, cs));
+    std::vector<hipEvent_t> ev_series(S.rounds, nullptr);
+    size_t ci = 0, si = 0;
+    for (int r = 0; r < S.rounds; ++r) {
+        void* E = d.ebuf[r % 2];
+        std::vector<hipEvent_t> joins;
+        int b = 0;
+        for (; ci < S.cp.size() && S.cp[ci].round == r; ++ci, ++b) {
+            const CharpolyLaunch& L = S.cp[ci];
+            hipStream_t bs = br[b % kBatchBranches];
+            HIP_TRY(hipStreamWaitEvent(bs, ev_prep, 0));
+            if (r >= 2) HIP_TRY(hipStreamWaitEvent(bs, ev_series[r - 2], 0));
+            const int grid = std::min(L.ntiles, kPersistentWaves);
+            HIP_TRY(gbs::launch_charpoly_batch(L.layout, L.s_rep, L.variant, S.max_n + 1, S.fp32 ? 1 : 0,
+                                               d.tiles + L.tile_begin, L.ntiles, d.items, c->binom, c->lbmap,
+                                               d.counters + L.counter, E, grid, bs));
+            hipEvent_t ej;
+            HIP_TRY(new_event(&ej));
+            HIP_TRY(hipEventRecord(ej, bs));
+            joins.push_back(ej);
+        }
+        for (hipEvent_t ej : joins) HIP_TRY(hipStreamWaitEvent(cs, ej, 0));
+        for (; si < S.se.size() && S.se[si].round == r; ++si) {
+            const SeriesLaunch& L = S.se[si];
+            HIP_TRY(gbs::launch_series_batch(L.n, S.fp32 ? 1 : 0, d.sblocks + L.block_begin, L.nblocks, d.tiles,
+                                             d.items, E, kSeriesPerThread, d.partials, cs));
+        }
+        HIP_TRY(new_event(&ev_series[r]));
+        HIP_TRY(hipEventRecord(ev_series[r], cs));
+    }
+    HIP_TRY(gbs::launch_item_reduce(d.pbeg, nitems, d.partials, d.out, d.abs, cs));
+    return GBS_OK;
+}
+
+}  // namespace gbs_host
+
+namespace {
 
 template <class T>
 gbs_status upload(T** dst, const std::vector<T>& src, size_t* bytes) {
@@ -122,209 +243,74 @@ gbs_status dmalloc(void** dst, size_t nb, size_t* bytes) {
     return GBS_OK;
 }
 
+void plan_free(gbs_plan* p) {
+    if (!p) return;
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    for (hipEvent_t e : p->events) hipEventDestroy(e);
+    if (p->t0) hipEventDestroy(p->t0);
+    if (p->t1) hipEventDestroy(p->t1);
+    for (hipStream_t s : p->br)
+        if (s) hipStreamDestroy(s);
+    if (p->cs) hipStreamDestroy(p->cs);
+    const BatchDev& d = p->d;
+    void* bufs[] = {p->staging, d.a0,       d.dv,       d.items,   d.in_off, d.dims,  d.tiles, d.sblocks,
+                    d.pbeg,     d.partials, d.counters, d.ebuf[0], d.ebuf[1], d.out,  d.abs};
+    for (void* b : bufs)
+        if (b) hipFree(b);
+    delete p;
+}
+
+std::vector<gbs::BatchItem> item_table(const BatchSchedule& S, double2* a0, double2* dv) {
+    std::vector<gbs::BatchItem> items(S.count);
+    for (int i = 0; i < S.count; ++i)
+        items[i] = gbs::BatchItem{a0 + S.a0_off[i], dv + S.d_off[i], 2 * S.npair[i], S.npair[i]};
+    return items;
+}
+
 // Builds schedule, buffers and graph for one tile size into p (freed by the
 // caller on failure).
 gbs_status plan_build_into(DevCtx* c, const std::vector<int>& dims, bool fp32, int64_t tile_subsets,
                            int64_t round_bytes, gbs_plan* p) {
     p->device = c->device;
-    p->count = (int)dims.size();
-    p->fp32 = fp32;
-    p->tile_subsets = tile_subsets;
-    const size_t vbytes = fp32 ? sizeof(float2) : sizeof(double2);
-    const int nitems = p->count;
-
-    // items
-    std::vector<int64_t> in_off(nitems), a0_off(nitems), d_off(nitems);
-    std::vector<int> npair(nitems);
-    int64_t ia = 0, iin = 0, id = 0;
-    for (int i = 0; i < nitems; ++i) {
-        const int N = dims[i], Np = N + (N & 1);
-        npair[i] = Np / 2;
-        in_off[i] = iin;
-        a0_off[i] = ia;
-        d_off[i] = id;
-        iin += (int64_t)N * N;
-        ia += (int64_t)Np * Np;
-        id += Np;
-        p->max_n = std::max(p->max_n, Np / 2);
-        p->subset_terms += (int64_t)1 << (Np / 2);
-        p->flops += gbs_yardstick_flops(N);
-    }
-    p->in_elems = iin;
-
-    // tiles: (item, s, rank range); series blocks and partial ranges per item
-    struct HostTile {
-        gbs::BatchTile t;
-        int inst, layout, variant;
-        double cost;
-        int round;
-    };
-    std::vector<HostTile> ht;
-    for (int i = 0; i < nitems; ++i) {
-        const int n = npair[i];
-        for (int s = 1; s <= n; ++s) {
-            const uint64_t cnt = binom_host(n, s);
-            const int lay = layout_for(c, n, s);
-            for (uint64_t r0 = 0; r0 < cnt; r0 += (uint64_t)tile_subsets) {
-                HostTile h{};
-                h.t.rank0 = r0;
-                h.t.count = std::min<uint64_t>((uint64_t)tile_subsets, cnt - r0);
-                h.t.item = i;
-                h.t.s = s;
-                h.layout = lay;
-                h.variant = gbs::charpoly_variant(lay, n);
-                h.inst = 4 * gbs::charpoly_instance(lay, s) + h.variant;
-                h.cost = subset_flops(n, s) * (double)h.t.count;
-                ht.push_back(h);
-            }
-        }
-    }
-    // partials: per item contiguous, in (item, s, rank) order
-    std::vector<int64_t> pbeg(nitems + 1, 0);
-    std::vector<int64_t> tile_pidx(ht.size());
-    {
-        int64_t pi = 0;
-        size_t k = 0;
-        for (int i = 0; i < nitems; ++i) {
-            pbeg[i] = pi;
-            while (k < ht.size() && ht[k].t.item == i) {
-                tile_pidx[k] = pi;
-                pi += (int64_t)((ht[k].t.count + kSeriesBlock - 1) / kSeriesBlock);
-                ++k;
-            }
-        }
-        pbeg[nitems] = pi;
-    }
-    // rounds: tiles in decreasing cost, filled up to round_bytes of coefficients
-    std::vector<size_t> order(ht.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return ht[a].cost > ht[b].cost; });
-    std::vector<int64_t> round_fill;
-    for (size_t k : order) {
-        const int64_t need = (int64_t)ht[k].t.count * 2 * (npair[ht[k].t.item] + 2) * (int64_t)vbytes;
-        int r = (int)round_fill.size() - 1;
-        if (r < 0 || round_fill[r] + need > round_bytes) {
-            round_fill.push_back(0);
-            r = (int)round_fill.size() - 1;
-        }
-        ht[k].t.eoff = (uint64_t)(round_fill[r] / (int64_t)vbytes);
-        round_fill[r] += need;
-        ht[k].round = r;
-    }
-    p->rounds = (int)round_fill.size();
-    const int64_t ebuf_bytes = round_fill.empty() ? 16 : *std::max_element(round_fill.begin(), round_fill.end());
-
-    // device tile array: grouped by (round, instance), largest first inside a group
-    std::vector<size_t> dorder(order);
-    std::stable_sort(dorder.begin(), dorder.end(), [&](size_t a, size_t b) {
-        if (ht[a].round != ht[b].round) return ht[a].round < ht[b].round;
-        return ht[a].inst < ht[b].inst;  // stable: cost order kept inside
-    });
-    std::vector<gbs::BatchTile> dtiles(dorder.size());
-    std::vector<int> pos_of(ht.size());
-    for (size_t q = 0; q < dorder.size(); ++q) {
-        dtiles[q] = ht[dorder[q]].t;
-        pos_of[dorder[q]] = (int)q;
-    }
-    for (size_t q = 0; q < dorder.size();) {
-        size_t e = q;
-        while (e < dorder.size() && ht[dorder[e]].round == ht[dorder[q]].round &&
-               ht[dorder[e]].inst == ht[dorder[q]].inst)
-            ++e;
-        const HostTile& h = ht[dorder[q]];
-        p->cp.push_back(
-            CharpolyLaunch{h.round, h.layout, h.t.s, h.inst, h.variant, (int)q, (int)(e - q), (int)p->cp.size()});
-        q = e;
-    }
-    p->ntiles = (int)dtiles.size();
-    // series blocks grouped by (round, n)
-    std::vector<gbs::SeriesBlock> sb;
-    std::map<std::pair<int, int>, std::vector<gbs::SeriesBlock>> by;
-    for (size_t k = 0; k < ht.size(); ++k) {
-        const int n = npair[ht[k].t.item];
-        auto& v = by[{ht[k].round, n}];
-        int64_t pi = tile_pidx[k];
-        for (uint64_t s0 = 0; s0 < ht[k].t.count; s0 += kSeriesBlock)
-            v.push_back(gbs::SeriesBlock{pos_of[k], (int)pi++, s0});
-    }
-    for (auto& kv : by) {
-        p->se.push_back(SeriesLaunch{kv.first.first, kv.first.second, (int)sb.size(), (int)kv.second.size()});
-        sb.insert(sb.end(), kv.second.begin(), kv.second.end());
-    }
-
-    // device buffers
+    BatchSchedule& S = p->S;
+    batch_schedule(c, dims, fp32, tile_subsets, round_bytes, S);
+    const int nitems = S.count;
     gbs_status st;
     size_t& B = p->bytes;
-    if ((st = dmalloc((void**)&p->staging, sizeof(double2) * (size_t)iin, &B)) != GBS_OK) return st;
-    if ((st = dmalloc((void**)&p->a0, sizeof(double2) * (size_t)ia, &B)) != GBS_OK) return st;
-    if ((st = dmalloc((void**)&p->dv, sizeof(double2) * (size_t)id, &B)) != GBS_OK) return st;
-    std::vector<gbs::BatchItem> hitems(nitems);
-    for (int i = 0; i < nitems; ++i)
-        hitems[i] = gbs::BatchItem{p->a0 + a0_off[i], p->dv + d_off[i], 2 * npair[i], npair[i]};
-    std::vector<int> hdims(dims.begin(), dims.end());
-    if ((st = upload(&p->items, hitems, &B)) != GBS_OK) return st;
-    if ((st = upload(&p->in_off, in_off, &B)) != GBS_OK) return st;
-    if ((st = upload(&p->dims, hdims, &B)) != GBS_OK) return st;
-    if ((st = upload(&p->tiles, dtiles, &B)) != GBS_OK) return st;
-    if ((st = upload(&p->sblocks, sb, &B)) != GBS_OK) return st;
-    if ((st = upload(&p->pbeg, pbeg, &B)) != GBS_OK) return st;
-    if ((st = dmalloc((void**)&p->partials, sizeof(double) * 5 * (size_t)std::max<int64_t>(1, pbeg[nitems]), &B)) !=
+    BatchDev& d = p->d;
+    if ((st = dmalloc((void**)&p->staging, sizeof(double2) * (size_t)S.in_elems, &B)) != GBS_OK) return st;
+    d.mats = p->staging;
+    if ((st = dmalloc((void**)&d.a0, sizeof(double2) * (size_t)S.a0_elems, &B)) != GBS_OK) return st;
+    if ((st = dmalloc((void**)&d.dv, sizeof(double2) * (size_t)S.d_elems, &B)) != GBS_OK) return st;
+    if ((st = upload(&d.items, item_table(S, d.a0, d.dv), &B)) != GBS_OK) return st;
+    if ((st = upload(&d.in_off, S.in_off, &B)) != GBS_OK) return st;
+    if ((st = upload(&d.dims, S.dims, &B)) != GBS_OK) return st;
+    if ((st = upload(&d.tiles, S.tiles, &B)) != GBS_OK) return st;
+    if ((st = upload(&d.sblocks, S.sblocks, &B)) != GBS_OK) return st;
+    if ((st = upload(&d.pbeg, S.pbeg, &B)) != GBS_OK) return st;
+    if ((st = dmalloc((void**)&d.partials, sizeof(double) * 5 * (size_t)std::max<int64_t>(1, S.pbeg[nitems]), &B)) !=
         GBS_OK)
         return st;
-    if ((st = dmalloc((void**)&p->counters, sizeof(unsigned) * std::max<size_t>(1, p->cp.size()), &B)) != GBS_OK)
+    if ((st = dmalloc((void**)&d.counters, sizeof(unsigned) * std::max<size_t>(1, S.cp.size()), &B)) != GBS_OK)
         return st;
-    for (int b = 0; b < 2 && b < p->rounds; ++b)
-        if ((st = dmalloc(&p->ebuf[b], (size_t)ebuf_bytes, &B)) != GBS_OK) return st;
-    if ((st = dmalloc((void**)&p->out, sizeof(double2) * nitems, &B)) != GBS_OK) return st;
-    if ((st = dmalloc((void**)&p->abs, sizeof(double) * nitems, &B)) != GBS_OK) return st;
+    for (int b = 0; b < 2 && b < S.rounds; ++b)
+        if ((st = dmalloc(&d.ebuf[b], (size_t)S.ebuf_bytes, &B)) != GBS_OK) return st;
+    if ((st = dmalloc((void**)&d.out, sizeof(double2) * nitems, &B)) != GBS_OK) return st;
+    if ((st = dmalloc((void**)&d.abs, sizeof(double) * nitems, &B)) != GBS_OK) return st;
 
     // graph capture
     HIP_TRY(hipStreamCreateWithFlags(&p->cs, hipStreamNonBlocking));
     for (hipStream_t& s : p->br) HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     HIP_TRY(hipEventCreate(&p->t0));
     HIP_TRY(hipEventCreate(&p->t1));
-    auto new_event = [&](hipEvent_t* e) -> hipError_t {
+    auto new_event = [p](hipEvent_t* e) -> hipError_t {
         hipError_t r = hipEventCreateWithFlags(e, hipEventDisableTiming);
         if (r == hipSuccess) p->events.push_back(*e);
         return r;
     };
     HIP_TRY(hipStreamBeginCapture(p->cs, hipStreamCaptureModeThreadLocal));
-    HIP_TRY(gbs::launch_fill_u32(p->counters, (int)std::max<size_t>(1, p->cp.size()), p->cs));
-    HIP_TRY(gbs::launch_batch_prep(p->staging, p->in_off, p->dims, p->items, nitems, p->cs));
-    hipEvent_t ev_prep;
-    HIP_TRY(new_event(&ev_prep));
-    HIP_TRY(hipEventRecord(ev_prep, p->cs));
-    std::vector<hipEvent_t> ev_series(p->rounds, nullptr);
-    size_t ci = 0, si = 0;
-    for (int r = 0; r < p->rounds; ++r) {
-        void* E = p->ebuf[r % 2];
-        std::vector<hipEvent_t> joins;
-        int b = 0;
-        for (; ci < p->cp.size() && p->cp[ci].round == r; ++ci, ++b) {
-            const CharpolyLaunch& L = p->cp[ci];
-            hipStream_t bs = p->br[b % kBranches];
-            HIP_TRY(hipStreamWaitEvent(bs, ev_prep, 0));
-            if (r >= 2) HIP_TRY(hipStreamWaitEvent(bs, ev_series[r - 2], 0));
-            const int grid = std::min(L.ntiles, kPersistentWaves);
-            HIP_TRY(gbs::launch_charpoly_batch(L.layout, L.s_rep, L.variant, p->max_n + 1, fp32 ? 1 : 0,
-                                               p->tiles + L.tile_begin,
-                                               L.ntiles, p->items, c->binom, c->lbmap, p->counters + L.counter, E,
-                                               grid, bs));
-            hipEvent_t ej;
-            HIP_TRY(new_event(&ej));
-            HIP_TRY(hipEventRecord(ej, bs));
-            joins.push_back(ej);
-        }
-        for (hipEvent_t ej : joins) HIP_TRY(hipStreamWaitEvent(p->cs, ej, 0));
-        for (; si < p->se.size() && p->se[si].round == r; ++si) {
-            const SeriesLaunch& S = p->se[si];
-            HIP_TRY(gbs::launch_series_batch(S.n, fp32 ? 1 : 0, p->sblocks + S.block_begin, S.nblocks, p->tiles,
-                                             p->items, E, kSeriesPerThread, p->partials, p->cs));
-        }
-        HIP_TRY(new_event(&ev_series[r]));
-        HIP_TRY(hipEventRecord(ev_series[r], p->cs));
-    }
-    HIP_TRY(gbs::launch_item_reduce(p->pbeg, nitems, p->partials, p->out, p->abs, p->cs));
+    if ((st = batch_enqueue(c, S, d, p->cs, p->br, new_event)) != GBS_OK) return st;
     HIP_TRY(hipStreamEndCapture(p->cs, &p->graph));
     HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
     return GBS_OK;
@@ -349,15 +335,158 @@ gbs_status plan_build(DevCtx* c, const std::vector<int>& dims, bool fp32, int64_
     return GBS_OK;
 }
 
-int kernel_nodes_of(const gbs_plan* p) { return 3 + (int)p->cp.size() + (int)p->se.size(); }
+}  // namespace
+
+// ---- eager runner -----------------------------------------------------------
+
+struct gbs_host::BatchRunner {
+    DevCtx* c = nullptr;
+    hipStream_t br[kBatchBranches] = {};
+    std::vector<hipEvent_t> events;
+    size_t ev_next = 0;
+    hipEvent_t upload_done = nullptr;
+    bool uploaded = false;
+    char* host_meta = nullptr;  // pinned staging of the meta arrays
+    size_t host_meta_cap = 0;
+    void* meta = nullptr;
+    size_t meta_cap = 0;
+    void *a0 = nullptr, *dv = nullptr, *partials = nullptr, *counters = nullptr, *out = nullptr, *abs = nullptr;
+    size_t a0_cap = 0, dv_cap = 0, partials_cap = 0, counters_cap = 0, out_cap = 0, abs_cap = 0;
+    void* ebuf[2] = {nullptr, nullptr};
+    size_t ebuf_cap[2] = {0, 0};
+};
+
+namespace gbs_host {
+
+gbs_status runner_create(DevCtx* c, BatchRunner** out) {
+    BatchRunner* r = new BatchRunner();
+    r->c = c;
+    *out = r;
+    for (hipStream_t& s : r->br) HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&r->upload_done, hipEventDisableTiming));
+    return GBS_OK;
+}
+
+void runner_free(BatchRunner* r) {
+    if (!r) return;
+    for (hipStream_t s : r->br)
+        if (s) hipStreamSynchronize(s);
+    for (hipEvent_t e : r->events) hipEventDestroy(e);
+    if (r->upload_done) hipEventDestroy(r->upload_done);
+    for (hipStream_t s : r->br)
+        if (s) hipStreamDestroy(s);
+    if (r->host_meta) hipHostFree(r->host_meta);
+    void* bufs[] = {r->meta, r->a0, r->dv, r->partials, r->counters, r->out, r->abs, r->ebuf[0], r->ebuf[1]};
+    for (void* b : bufs)
+        if (b) hipFree(b);
+    delete r;
+}
+
+double2* runner_out(BatchRunner* r) { return static_cast<double2*>(r->out); }
+
+gbs_status runner_run(BatchRunner* r, const BatchSchedule& S, const double2* mats_dev, hipStream_t st,
+                      const std::function<gbs_status(const int64_t* in_off_dev, const int* dims_dev)>& before_sum) {
+    if (S.count == 0) return GBS_OK;
+    // the pinned staging and the buffers may be reused only once the previous run has finished with them
+    if (r->uploaded) HIP_TRY(hipEventSynchronize(r->upload_done));
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t n_items = sizeof(gbs::BatchItem) * S.count, n_inoff = sizeof(int64_t) * S.in_off.size(),
+                 n_dims = sizeof(int) * S.dims.size(), n_tiles = sizeof(gbs::BatchTile) * S.tiles.size(),
+                 n_sb = sizeof(gbs::SeriesBlock) * S.sblocks.size(), n_pbeg = sizeof(int64_t) * S.pbeg.size();
+    const size_t o_items = 0, o_inoff = align(o_items + n_items), o_dims = align(o_inoff + n_inoff),
+                 o_tiles = align(o_dims + n_dims), o_sb = align(o_tiles + n_tiles), o_pbeg = align(o_sb + n_sb),
+                 total = align(o_pbeg + n_pbeg);
+    const size_t npart = 5 * (size_t)std::max<int64_t>(1, S.pbeg[S.count]);
+    const bool grow = r->meta_cap < total || r->a0_cap < sizeof(double2) * (size_t)S.a0_elems ||
+                      r->dv_cap < sizeof(double2) * (size_t)S.d_elems || r->partials_cap < sizeof(double) * npart ||
+                      r->counters_cap < sizeof(unsigned) * std::max<size_t>(1, S.cp.size()) ||
+                      r->out_cap < sizeof(double2) * S.count || r->abs_cap < sizeof(double) * S.count ||
+                      r->ebuf_cap[0] < (size_t)S.ebuf_bytes || (S.rounds > 1 && r->ebuf_cap[1] < (size_t)S.ebuf_bytes);
+    if (grow) {
+        // buffers still in use by earlier work on st are released only after it
+        HIP_TRY(hipStreamSynchronize(st));
+        gbs_status e;
+        if ((e = ensure_buffer(&r->meta, &r->meta_cap, total, 1)) != GBS_OK) return e;
+        if ((e = ensure_buffer(&r->a0, &r->a0_cap, sizeof(double2) * std::max<size_t>(1, S.a0_elems), 1)) != GBS_OK)
+            return e;
+        if ((e = ensure_buffer(&r->dv, &r->dv_cap, sizeof(double2) * std::max<size_t>(1, S.d_elems), 1)) != GBS_OK)
+            return e;
+        if ((e = ensure_buffer(&r->partials, &r->partials_cap, sizeof(double) * npart, 1)) != GBS_OK) return e;
+        if ((e = ensure_buffer(&r->counters, &r->counters_cap, sizeof(unsigned) * std::max<size_t>(1, S.cp.size()),
+                               1)) != GBS_OK)
+            return e;
+        if ((e = ensure_buffer(&r->out, &r->out_cap, sizeof(double2) * S.count, 1)) != GBS_OK) return e;
+        if ((e = ensure_buffer(&r->abs, &r->abs_cap, sizeof(double) * S.count, 1)) != GBS_OK) return e;
+        for (int b = 0; b < 2 && b < S.rounds; ++b)
+            if ((e = ensure_buffer(&r->ebuf[b], &r->ebuf_cap[b], (size_t)S.ebuf_bytes, 1)) != GBS_OK) return e;
+    }
+    if (r->host_meta_cap < total) {
+        if (r->host_meta) HIP_TRY(hipHostFree(r->host_meta));
+        r->host_meta = nullptr;
+        r->host_meta_cap = 0;
+        HIP_TRY(hipHostMalloc((void**)&r->host_meta, total, hipHostMallocDefault));
+        r->host_meta_cap = total;
+    }
+    const std::vector<gbs::BatchItem> items = item_table(S, (double2*)r->a0, (double2*)r->dv);
+    char* h = r->host_meta;
+    std::memcpy(h + o_items, items.data(), n_items);
+    std::memcpy(h + o_inoff, S.in_off.data(), n_inoff);
+    std::memcpy(h + o_dims, S.dims.data(), n_dims);
+    if (n_tiles) std::memcpy(h + o_tiles, S.tiles.data(), n_tiles);
+    if (n_sb) std::memcpy(h + o_sb, S.sblocks.data(), n_sb);
+    std::memcpy(h + o_pbeg, S.pbeg.data(), n_pbeg);
+    HIP_TRY(hipMemcpyAsync(r->meta, h, total, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(r->upload_done, st));
+    r->uploaded = true;
+
+    char* m = static_cast<char*>(r->meta);
+    BatchDev d;
+    d.mats = mats_dev;
+    d.a0 = (double2*)r->a0;
+    d.dv = (double2*)r->dv;
+    d.items = (gbs::BatchItem*)(m + o_items);
+    d.in_off = (int64_t*)(m + o_inoff);
+    d.dims = (int*)(m + o_dims);
+    d.tiles = (gbs::BatchTile*)(m + o_tiles);
+    d.sblocks = (gbs::SeriesBlock*)(m + o_sb);
+    d.pbeg = (int64_t*)(m + o_pbeg);
+    d.partials = (double*)r->partials;
+    d.counters = (unsigned*)r->counters;
+    d.ebuf[0] = r->ebuf[0];
+    d.ebuf[1] = r->ebuf[1];
+    d.out = (double2*)r->out;
+    d.abs = (double*)r->abs;
+    if (before_sum) {
+        const gbs_status e = before_sum(d.in_off, d.dims);
+        if (e != GBS_OK) return e;
+    }
+    r->ev_next = 0;
+    auto new_event = [r](hipEvent_t* e) -> hipError_t {
+        if (r->ev_next == r->events.size()) {
+            hipEvent_t ev;
+            const hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (err != hipSuccess) return err;
+            r->events.push_back(ev);
+        }
+        *e = r->events[r->ev_next++];
+        return hipSuccess;
+    };
+    return batch_enqueue(r->c, S, d, st, r->br, new_event);
+}
+
+}  // namespace gbs_host
+
+namespace {
+
+int kernel_nodes_of(const gbs_plan* p) { return 3 + (int)p->S.cp.size() + (int)p->S.se.size(); }
 
 gbs_status plan_run(gbs_plan* p, const gbs_z* mats_dev, gbs_z* out_dev, double* abs_dev, hipStream_t s) {
-    if (p->in_elems > 0)
-        HIP_TRY(hipMemcpyAsync(p->staging, mats_dev, sizeof(double2) * (size_t)p->in_elems, hipMemcpyDeviceToDevice,
+    if (p->S.in_elems > 0)
+        HIP_TRY(hipMemcpyAsync(p->staging, mats_dev, sizeof(double2) * (size_t)p->S.in_elems, hipMemcpyDeviceToDevice,
                                s));
     HIP_TRY(hipGraphLaunch(p->exec, s));
-    if (out_dev) HIP_TRY(hipMemcpyAsync(out_dev, p->out, sizeof(double2) * p->count, hipMemcpyDeviceToDevice, s));
-    if (abs_dev) HIP_TRY(hipMemcpyAsync(abs_dev, p->abs, sizeof(double) * p->count, hipMemcpyDeviceToDevice, s));
+    if (out_dev) HIP_TRY(hipMemcpyAsync(out_dev, p->d.out, sizeof(double2) * p->S.count, hipMemcpyDeviceToDevice, s));
+    if (abs_dev) HIP_TRY(hipMemcpyAsync(abs_dev, p->d.abs, sizeof(double) * p->S.count, hipMemcpyDeviceToDevice, s));
     return GBS_OK;
 }
 
@@ -459,20 +588,20 @@ gbs_status gbs_batch_plan_create(const int32_t* dims, int32_t count, gbs_precisi
 
 gbs_status gbs_batch_plan_info(const gbs_plan* plan, gbs_batch_info* info) {
     if (!plan || !info) return fail(GBS_E_ARG, "null plan or info");
-    info->items = plan->count;
-    info->tiles = plan->ntiles;
-    info->rounds = plan->rounds;
+    info->items = plan->S.count;
+    info->tiles = (int)plan->S.tiles.size();
+    info->rounds = plan->S.rounds;
     info->kernel_nodes = kernel_nodes_of(plan);
-    info->subset_terms = plan->subset_terms;
-    info->tile_subsets = plan->tile_subsets;
+    info->subset_terms = plan->S.subset_terms;
+    info->tile_subsets = plan->S.tile_subsets;
     info->workspace_bytes = (int64_t)plan->bytes;
-    info->yardstick_flops = plan->flops;
+    info->yardstick_flops = plan->S.flops;
     info->tune_ms = plan->tune_ms;
     return GBS_OK;
 }
 
 gbs_status gbs_batch_run(gbs_plan* plan, const gbs_z* mats_dev, gbs_z* out_dev, double* abs_sum_dev, void* stream) {
-    if (!plan || (!mats_dev && plan->in_elems > 0) || (!out_dev && plan->count > 0))
+    if (!plan || (!mats_dev && plan->S.in_elems > 0) || (!out_dev && plan->S.count > 0))
         return fail(GBS_E_ARG, "bad batch run arguments");
     std::lock_guard<std::mutex> lock(g_mutex);
     if (hipSetDevice(plan->device) != hipSuccess) return fail(GBS_E_DEVICE, "hipSetDevice failed");

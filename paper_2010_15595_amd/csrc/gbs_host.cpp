@@ -151,6 +151,8 @@ void ctx_destroy(DevCtx* c) {
     hipFree(c->partials);
     hipFree(c->masks);
     hipFree(c->terms);
+    runner_free(c->runner);
+    hipFree(c->smats);
     if (c->done) hipEventDestroy(c->done);
     if (c->t0) hipEventDestroy(c->t0);
     if (c->t1) hipEventDestroy(c->t1);

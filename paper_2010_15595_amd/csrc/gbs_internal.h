@@ -3,9 +3,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <complex>
 #include <cstdint>
+#include <functional>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/gbs_lhaf.h"
 #include "lhaf_kernels.h"
@@ -24,8 +27,13 @@ gbs_status fail(gbs_status st, const char* fmt, ...);
     } while (0)
 
 uint64_t binom_host(int a, int b);
+// Cholesky factorisation Q = L L^H of a Hermitian matrix (row-major n x n, in
+// place, lower triangle); false when not positive definite.
+bool cholesky(std::vector<std::complex<double>>& L, int n);
 // Flop yardstick of one subset of size s of an n-pair loop hafnian.
 double subset_flops(int n, int s);
+
+struct BatchRunner;
 
 // Per-device workspace.  All library calls take g_mutex, so one context is
 // used by one call at a time; `done` orders reuse across caller streams.
@@ -46,6 +54,9 @@ struct DevCtx {
     uint64_t* masks = nullptr;
     double2* terms = nullptr;
     size_t masks_cap = 0;
+    BatchRunner* runner = nullptr;  // eager batch runner of the sampling chain, created on first use
+    void* smats = nullptr;          // packed loop-hafnian matrices of one sampling step
+    size_t smats_cap = 0;           // bytes
     // lane grid per (n, s); -1 = heuristic default
     int layout[gbs::kMaxPairs + 1][gbs::kMaxPairs + 1];
     bool tuned[gbs::kMaxPairs + 1];
@@ -67,5 +78,82 @@ gbs_status maybe_tune(DevCtx* c, int n);
 gbs_status ensure_buffer(void** p, size_t* cap, size_t need, size_t elem);
 // Times each valid lane grid per subset size of an n-pair loop hafnian.
 gbs_status autotune_impl(DevCtx* c, int n, gbs_tune_report* rep);
+
+// ---- batches of loop hafnians (gbs_batch.cpp) ----
+
+// One persistent per-subset launch of a batch schedule.
+struct CharpolyLaunch {
+    int round, layout, s_rep, inst, variant;
+    int tile_begin, ntiles;  // range in the device tile array
+    int counter;
+};
+// One series launch (all blocks of one round and one n).
+struct SeriesLaunch {
+    int round, n;
+    int block_begin, nblocks;
+};
+
+// Host-side schedule of a batch of loop hafnians of dimensions `dims`:
+// tiles, rounds over two coefficient buffers, launches, and the sizes of the
+// device arrays they need.  Built without touching the device.
+struct BatchSchedule {
+    int count = 0;
+    bool fp32 = false;
+    int64_t tile_subsets = 0;
+    int rounds = 0;
+    int max_n = 0;
+    int64_t subset_terms = 0;
+    double flops = 0.0;
+    int64_t in_elems = 0, a0_elems = 0, d_elems = 0;  // packed input, padded A0 blocks, loop weights
+    int64_t ebuf_bytes = 16;                          // per coefficient buffer
+    std::vector<int> dims, npair;
+    std::vector<int64_t> in_off, a0_off, d_off;
+    std::vector<gbs::BatchTile> tiles;  // device order: (round, instance), largest first
+    std::vector<gbs::SeriesBlock> sblocks;
+    std::vector<int64_t> pbeg;          // partial records of item i: [pbeg[i], pbeg[i+1])
+    std::vector<CharpolyLaunch> cp;
+    std::vector<SeriesLaunch> se;
+};
+void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, int64_t tile_subsets,
+                    int64_t round_bytes, BatchSchedule& S);
+
+// Device arrays a schedule runs on.  `mats` is the packed input.
+struct BatchDev {
+    const double2* mats = nullptr;
+    double2 *a0 = nullptr, *dv = nullptr;
+    gbs::BatchItem* items = nullptr;
+    int64_t* in_off = nullptr;
+    int* dims = nullptr;
+    gbs::BatchTile* tiles = nullptr;
+    gbs::SeriesBlock* sblocks = nullptr;
+    int64_t* pbeg = nullptr;
+    double* partials = nullptr;
+    unsigned* counters = nullptr;
+    void* ebuf[2] = {nullptr, nullptr};
+    double2* out = nullptr;
+    double* abs = nullptr;
+};
+constexpr int kBatchBranches = 4;  // parallel streams of the per-subset launches of one round
+// Issues the whole schedule: counter fill, prep, rounds of per-subset launches
+// on the branch streams (joined into `cs` through events from `new_event`),
+// series launches and the per-item reduction, all ordered after prior work on
+// `cs`.  Works eagerly and under stream capture alike.
+gbs_status batch_enqueue(DevCtx* c, const BatchSchedule& S, const BatchDev& d, hipStream_t cs, hipStream_t* br,
+                         const std::function<hipError_t(hipEvent_t*)>& new_event);
+
+// Eager runner of batch schedules on reusable, growing device buffers, for
+// callers whose batches change from one run to the next.
+struct BatchRunner;
+gbs_status runner_create(DevCtx* c, BatchRunner** out);
+void runner_free(BatchRunner* r);
+// Runs the batch of dimensions S.dims on packed matrices mats_dev (device).
+// The meta arrays (items, offsets, tiles) are uploaded first; `before_sum`
+// (optional) is then enqueued on `st` so that it can fill mats_dev from them
+// (it receives the device in_off and dims arrays).  Results: out[i] and
+// abs[i] in the runner's device buffers (runner_out / runner_abs), valid
+// after `st` completes.
+gbs_status runner_run(BatchRunner* r, const BatchSchedule& S, const double2* mats_dev, hipStream_t st,
+                      const std::function<gbs_status(const int64_t* in_off_dev, const int* dims_dev)>& before_sum);
+double2* runner_out(BatchRunner* r);
 
 }  // namespace gbs_host

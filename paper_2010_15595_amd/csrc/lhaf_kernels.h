@@ -88,6 +88,32 @@ hipError_t launch_item_reduce(const int64_t* pbeg, int nitems, const double* par
 hipError_t launch_batch_prep(const double2* mats, const int64_t* in_off, const int* N, BatchItem* items, int nitems,
                              hipStream_t st);
 hipError_t launch_fill_u32(unsigned* p, int count, hipStream_t st);
+
+// ---- conditional sampling chain (Sec. III) ----
+constexpr int kMaxSamplerModes = 128;  // modes of a sampled state
+constexpr int kMaxCutoff = 64;         // photon-number cutoff per mode
+
+// One lockstep step k (1-based) of the chain over nsamples samples: item
+// b * (cutoff + 1) + j of the batch is the loop-hafnian matrix of pattern
+// (s_1, .., s_{k-1}, j) of sample b's conditional state of modes 1..k.
+struct SamplerStep {
+    int M, k, cutoff, nsamples;
+    const double2* Bk;      // k x k, B of the conditional state (heterodyne outcomes of modes k+1..M)
+    const double2* ck;      // k: loop weights at zero outcome
+    const double2* Fk;      // k x 2(M - k): gain of the loop weights on [beta_B; conj(beta_B)]
+    const double2* beta;    // nsamples x (M - 1): outcomes of modes 2..M
+    const int* samples;     // M x nsamples (mode-major): draws of modes 1..k-1
+    const int64_t* in_off;  // per item: element offset of its matrix in mats
+    const int* dims;        // per item: dimension
+    double2* mats;          // packed matrices (output)
+};
+// beta[b * dim/2 + i] = x_i + i x_{dim/2 + i}, x = mean + L z_b, z_b = normals[b * dim ..]
+hipError_t launch_heterodyne(const double* L, const double* mean, int dim, const double* normals, int nsamples,
+                             double2* beta, hipStream_t st);
+hipError_t launch_sampler_build(const SamplerStep& p, hipStream_t st);
+// draw[b] from lh[b * (cutoff + 1) + j] and u[b]; probs (nullable) row b at probs + b * probs_stride.
+hipError_t launch_sampler_draw(const double2* lh, int nsamples, int cutoff, const double* u, int* draw, double* probs,
+                               int64_t probs_stride, hipStream_t st);
 hipError_t launch_series(int n, const LaunchPhase2& p, hipStream_t st);
 hipError_t launch_final_reduce(const double* partials, int64_t np, double2* out, double* abs_out, hipStream_t st);
 hipError_t launch_prep(const double2* A, int N, int64_t lda, int Np, double2* A0, double2* d, hipStream_t st);

@@ -146,3 +146,23 @@ def test_mixed_probability_validation():
     al = st["alpha_vec"].copy()
     al[2] = 3.0
     _expect(-1, gbs.probability_mixed, Q, al, [1, 1])
+
+
+def test_sample_pure_validation():
+    """Argument errors of gbs_sample_pure are reported before any device work."""
+    st = workloads.pure_state(3, 0.5, 0.2, seed=4)
+    Q, al = st["Q"], st["alpha_vec"]
+    rng = np.random.default_rng(0)
+    z, u = rng.standard_normal((4, 4)), rng.random((4, 3))
+    _expect(-1, gbs.sample_pure, Q, al, -1, z, u)
+    ubad = u.copy()
+    ubad[1, 2] = 1.0  # uniforms live in [0, 1)
+    _expect(-1, gbs.sample_pure, Q, al, 4, z, ubad)
+    zbad = z.copy()
+    zbad[0, 0] = np.nan
+    _expect(-3, gbs.sample_pure, Q, al, 4, zbad, u)
+    _expect(-4, gbs.sample_pure, Q, al, 65, z, u)
+    mixed = Q + np.diag([0.1] * 6)
+    _expect(-5, gbs.sample_pure, mixed, al, 4, z, u)
+    big = workloads.pure_state(129, 0.1, 0.1, seed=1)
+    _expect(-4, gbs.sample_pure, big["Q"], big["alpha_vec"], 2, np.zeros((1, 256)), np.zeros((1, 129)))
