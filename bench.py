@@ -332,8 +332,9 @@ def main():
     ap.add_argument("--N", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "fp32comp"], default="fp64",
-                    help="fp32comp: La Budde, series and per-lane sums in complex FP32 (Hessenberg FP64)")
+    ap.add_argument("--precision", choices=["fp64", "fp32comp", "dd"], default="fp64",
+                    help="fp32comp: La Budde, series and per-lane sums in complex FP32 (Hessenberg FP64); "
+                         "dd: every step in double-double (single evaluations, N <= 56)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the lane-grid autotuner (use the heuristic or GBS_AUTOTUNE_CACHE)")
     ap.add_argument("--print-source-hash", action="store_true",
@@ -398,7 +399,7 @@ def main():
     terms = float(1 << n)
     flops = gbs.yardstick_flops(N)
 
-    prec = gbs.GBS_FP64 if args.precision == "fp64" else gbs.GBS_FP32_COMP
+    prec = {"fp64": gbs.GBS_FP64, "fp32comp": gbs.GBS_FP32_COMP, "dd": gbs.GBS_DD}[args.precision]
     torch.cuda.set_device(0)
     gbs.init(0)
     dev = torch.device("cuda:0")
@@ -408,7 +409,7 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     tuned = None
-    if not args.no_autotune:
+    if not args.no_autotune and args.precision != "dd":
         t0 = time.perf_counter()
         rep = gbs.autotune(n)
         tuned = {s: lay for s, (lay, _) in rep.items()}
@@ -457,7 +458,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128" if args.precision == "fp64" else "c128 Hessenberg + c64 La Budde/series (compensated)",
+        "dtype": {"fp64": "c128", "fp32comp": "c128 Hessenberg + c64 La Budde/series (compensated)",
+                  "dd": "double-double complex (~106-bit significand)"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": f"loop hafnian N={N} of a 100-mode pure Gaussian state (Haar U, r=1.2, sigma=0.1), "

@@ -53,9 +53,16 @@ typedef enum {
 
 typedef enum {
     GBS_FP64 = 0,      /* all steps in IEEE binary64 */
-    GBS_FP32_COMP = 1  /* Hessenberg reduction and all cross-lane / final sums in
+    GBS_FP32_COMP = 1, /* Hessenberg reduction and all cross-lane / final sums in
                           binary64; La Budde, power-trace series and the per-lane
                           compensated (TwoSum) sums in complex binary32 */
+    GBS_DD = 2         /* every step of every subset term and every sum in
+                          double-double (~106-bit significand; the paper's CPU
+                          code uses x87 long double, 64 bits): single
+                          evaluations with N <= 56 only (GBS_E_TOO_LARGE above,
+                          GBS_E_UNSUPPORTED for batch plans and the sampler).
+                          The result is hi + lo: out receives hi, and
+                          gbs_diag.lhaf_lo the low part */
 } gbs_precision;
 
 /* Optional diagnostics of one loop-hafnian evaluation. */
@@ -66,6 +73,8 @@ typedef struct {
     double kernel_ms;      /* GPU time of the subset sum (HIP events)           */
     int32_t n_pairs;       /* n                                                 */
     int32_t launches;      /* kernel launches issued                            */
+    gbs_z lhaf_lo;         /* GBS_DD: low part of the result (lhaf = out + lhaf_lo);
+                              0 for the other precisions                         */
 } gbs_diag;
 
 /* ---- library lifetime ---------------------------------------------------- */

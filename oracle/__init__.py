@@ -324,9 +324,10 @@ def lhaf_enumerate(A, loops=True):
     return rec(tuple(range(N)))
 
 
-def lhaf_mpmath(A, dps=50):
+def lhaf_mpmath(A, dps=50, exact=False):
     """The definition evaluated in mpmath at ``dps`` digits (memoised over
-    vertex subsets), for accuracy references at N <= 16."""
+    vertex subsets), for accuracy references at N <= 16.  Returns a Python
+    complex (rounded to double), or with exact=True the mpmath value itself."""
     import mpmath
 
     A = np.asarray(A, dtype=np.complex128)
@@ -345,4 +346,4 @@ def lhaf_mpmath(A, dps=50):
                 tot += M[i][j] * f[rest & ~(1 << j)]
                 r &= r - 1
             f[mask] = tot
-        return complex(f[(1 << N) - 1])
+        return f[(1 << N) - 1] if exact else complex(f[(1 << N) - 1])

@@ -8,6 +8,7 @@ the C ABI of include/gbs_lhaf.h.  This package is the thin Python binding.
 """
 from ._lib import (  # noqa: F401
     BatchPlan,
+    GBS_DD,
     GBS_FP32_COMP,
     GBS_FP64,
     GbsError,

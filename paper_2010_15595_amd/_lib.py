@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libgbs_lhaf.so")
 
 GBS_FP64 = 0
 GBS_FP32_COMP = 1
+GBS_DD = 2
 
 STATUS = {
     0: "GBS_OK", -1: "GBS_E_ARG", -2: "GBS_E_NOT_SYMMETRIC", -3: "GBS_E_NONFINITE", -4: "GBS_E_TOO_LARGE",
@@ -34,7 +35,8 @@ class gbs_z(ctypes.Structure):
 
 class gbs_diag(ctypes.Structure):
     _fields_ = [("abs_sum", ctypes.c_double), ("kappa", ctypes.c_double), ("subset_terms", ctypes.c_uint64),
-                ("kernel_ms", ctypes.c_double), ("n_pairs", ctypes.c_int32), ("launches", ctypes.c_int32)]
+                ("kernel_ms", ctypes.c_double), ("n_pairs", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("lhaf_lo", gbs_z)]
 
 
 class gbs_tune_report(ctypes.Structure):
@@ -160,7 +162,9 @@ def _zp(a):
 
 
 def _diag_dict(d):
-    return {f: getattr(d, f) for f, _ in gbs_diag._fields_}
+    out = {f: getattr(d, f) for f, _ in gbs_diag._fields_}
+    out["lhaf_lo"] = complex(d.lhaf_lo.re, d.lhaf_lo.im)
+    return out
 
 
 def init(device=0):

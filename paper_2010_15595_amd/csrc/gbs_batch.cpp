@@ -497,6 +497,7 @@ extern "C" {
 gbs_status gbs_batch_plan_create(const int32_t* dims, int32_t count, gbs_precision prec, int32_t flags,
                                  gbs_plan** plan) {
     if (!plan || count < 0 || (count > 0 && !dims)) return fail(GBS_E_ARG, "bad batch arguments");
+    if (prec == GBS_DD) return fail(GBS_E_UNSUPPORTED, "batch plans run in FP64 or FP32_COMP");
     if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
     std::vector<int> dv(count);
     for (int i = 0; i < count; ++i) {

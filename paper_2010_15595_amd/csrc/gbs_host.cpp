@@ -125,7 +125,7 @@ gbs_status ctx_create(int device, DevCtx** out) {
     HIP_TRY(hipMalloc((void**)&c->A0, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
     HIP_TRY(hipMalloc((void**)&c->dvec, sizeof(double2) * GBS_MAX_DIM));
     HIP_TRY(hipMalloc((void**)&c->Ain, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
-    HIP_TRY(hipMalloc((void**)&c->res, sizeof(double2) * 2));
+    HIP_TRY(hipMalloc((void**)&c->res, sizeof(double2) * 3));
     HIP_TRY(hipEventRecord(c->done, c->stream));
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
@@ -236,15 +236,66 @@ gbs_status expand_impl(const gbs_z* B, int32_t M, int64_t ldb, const gbs_z* gamm
 }
 
 // Subset-sum schedule on prepared workspace (ctx->A0, ctx->dvec).
+// Double-double subset sum: per size class and chunk, one workgroup per subset
+// writes its term, a block reduction folds them into dd partials, and one
+// final fixed-order dd reduction gives hi (out_dev) and lo (lo_dev) parts.
+gbs_status run_sum_dd(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double2* lo_dev, double* abs_dev,
+                      int* launches) {
+    const int n = Np / 2, D = n + 1;
+    if (n > gbs::kMaxDdPairs)
+        return fail(GBS_E_TOO_LARGE, "double-double path: dimension %d exceeds %d", Np, 2 * gbs::kMaxDdPairs);
+    constexpr int kDdPer = 8;  // terms per lane in the block reduction
+    const uint64_t per_block = 64ull * kDdPer;
+    uint64_t max_len = 0, total_blocks = 0;
+    for (int s = 1; s <= n; ++s) {
+        const uint64_t cnt = binom_host(n, s);
+        for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
+            const uint64_t len = std::min(kChunk, cnt - st0);
+            max_len = std::max(max_len, len);
+            total_blocks += (len + per_block - 1) / per_block;
+        }
+    }
+    gbs_status s1 = ensure_buffer(&c->E, &c->E_cap, (size_t)max_len * 4 * sizeof(double), 1);
+    if (s1 != GBS_OK) return s1;
+    s1 = ensure_buffer((void**)&c->partials, &c->partials_cap, (size_t)total_blocks * 5, sizeof(double));
+    if (s1 != GBS_OK) return s1;
+    uint64_t poff = 0;
+    int nl = 0;
+    for (int s = 1; s <= n; ++s) {
+        const uint64_t cnt = binom_host(n, s);
+        const double sign = ((n - s) & 1) ? -1.0 : 1.0;
+        for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
+            const uint64_t len = std::min(kChunk, cnt - st0);
+            HIP_TRY(timed_launch(kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st, [&] {
+                return gbs::launch_charpoly_dd(c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, sign, c->E, st);
+            }));
+            HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, st, [&] {
+                return gbs::launch_dd_block_reduce(c->E, len, kDdPer, c->partials + 5 * poff, nullptr, st);
+            }));
+            poff += (len + per_block - 1) / per_block;
+            nl += 2;
+        }
+    }
+    HIP_TRY(timed_launch(kProfReduce, 0.0, 0.0, st, [&] {
+        return gbs::launch_dd_final_reduce(c->partials, (int64_t)poff, out_dev, lo_dev, abs_dev, st);
+    }));
+    if (launches) *launches = nl + 1;
+    return GBS_OK;
+}
+
 gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* abs_dev, int* launches,
-                   bool fp32) {
+                   gbs_precision prec, double2* lo_dev = nullptr) {
     const int n = Np / 2;
     int nl = 0;
     if (n == 0) {
         HIP_TRY(gbs::launch_scalar_set(out_dev, make_double2(1.0, 0.0), abs_dev, 1.0, st));
+        if (lo_dev) HIP_TRY(gbs::launch_scalar_set(lo_dev, make_double2(0.0, 0.0), nullptr, 0.0, st));
         if (launches) *launches = 1;
         return GBS_OK;
     }
+    if (prec == GBS_DD) return run_sum_dd(c, Np, st, out_dev, lo_dev, abs_dev, launches);
+    if (lo_dev) HIP_TRY(gbs::launch_scalar_set(lo_dev, make_double2(0.0, 0.0), nullptr, 0.0, st));
+    const bool fp32 = prec == GBS_FP32_COMP;
     const int D = n + 1;
     uint64_t max_len = 0, total_blocks = 0;
     const uint64_t per_block = 64ull * kPerThread;
@@ -285,7 +336,7 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
 }
 
 // Full evaluation of an expanded host matrix (N x N, diagonal = loop weights).
-gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* diag, bool fp32) {
+gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* diag, gbs_precision prec) {
     DevCtx* c = nullptr;
     gbs_status st = current_ctx(&c);
     if (st != GBS_OK) return st;
@@ -297,10 +348,10 @@ gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* dia
     HIP_TRY(hipEventRecord(c->t0, c->stream));
     if (Np > 0) HIP_TRY(gbs::launch_prep(c->Ain, N, N, Np, c->A0, c->dvec, c->stream));
     int launches = 0;
-    st = run_sum(c, Np, c->stream, c->res, reinterpret_cast<double*>(c->res + 1), &launches, fp32);
+    st = run_sum(c, Np, c->stream, c->res, reinterpret_cast<double*>(c->res + 1), &launches, prec, c->res + 2);
     if (st != GBS_OK) return st;
     HIP_TRY(hipEventRecord(c->t1, c->stream));
-    double2 h[2];
+    double2 h[3];
     HIP_TRY(hipMemcpyAsync(h, c->res, sizeof h, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipEventRecord(c->done, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -316,6 +367,7 @@ gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* dia
         diag->kernel_ms = ms;
         diag->n_pairs = Np / 2;
         diag->launches = launches;
+        diag->lhaf_lo = gbs_z{h[2].x, h[2].y};
     }
     return GBS_OK;
 }
@@ -532,7 +584,7 @@ gbs_status gbs_pure_state(const gbs_z* Q, const gbs_z* alpha, int32_t M, gbs_z* 
 gbs_status gbs_probability_mixed(const gbs_z* Q, const gbs_z* alpha, const int32_t* pattern, int32_t M,
                                  gbs_precision prec, double* p_out, gbs_z* lhaf_out, gbs_diag* diag) {
     if (!p_out || (M > 0 && !pattern)) return fail(GBS_E_ARG, "null output or pattern");
-    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP && prec != GBS_DD) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
     int64_t photons = 0;
     for (int i = 0; i < M; ++i) {
         if (pattern[i] < 0) return fail(GBS_E_ARG, "negative photon number at mode %d", i);
@@ -566,7 +618,7 @@ gbs_status gbs_probability_mixed(const gbs_z* Q, const gbs_z* alpha, const int32
     gbs_z lh{1.0, 0.0};
     {
         std::lock_guard<std::mutex> lock(g_mutex);
-        st = lhaf_host_matrix(As.data(), N, &lh, diag, prec == GBS_FP32_COMP);
+        st = lhaf_host_matrix(As.data(), N, &lh, diag, prec);
     }
     if (st != GBS_OK) return st;
     const double scale = std::exp(-0.5 * G.quad.real() - 0.5 * G.logdet - lfactorial_sum(pattern, M));
@@ -578,18 +630,18 @@ gbs_status gbs_probability_mixed(const gbs_z* Q, const gbs_z* alpha, const int32
 gbs_status gbs_lhaf(const gbs_z* A, int32_t M, int64_t lda, const gbs_z* gamma, const int32_t* mult,
                     gbs_precision prec, gbs_z* out, gbs_diag* diag) {
     if (!out) return fail(GBS_E_ARG, "null output");
-    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP && prec != GBS_DD) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
     std::vector<gbs_z> Aexp;
     int32_t N = 0;
     gbs_status st = expand_impl(A, M, lda, gamma, mult, Aexp, &N);
     if (st != GBS_OK) return st;
     std::lock_guard<std::mutex> lock(g_mutex);
-    return lhaf_host_matrix(Aexp.data(), N, out, diag, prec == GBS_FP32_COMP);
+    return lhaf_host_matrix(Aexp.data(), N, out, diag, prec);
 }
 
 gbs_status gbs_haf(const gbs_z* A, int32_t N, int64_t lda, gbs_precision prec, gbs_z* out, gbs_diag* diag) {
     if (!out) return fail(GBS_E_ARG, "null output");
-    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP && prec != GBS_DD) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
     gbs_status st = check_matrix(A, N, lda, "A", true);
     if (st != GBS_OK) return st;
     if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d exceeds %d", N, GBS_MAX_DIM);
@@ -603,13 +655,13 @@ gbs_status gbs_haf(const gbs_z* A, int32_t N, int64_t lda, gbs_precision prec, g
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j) A0[(size_t)i * N + j] = (i == j) ? gbs_z{0.0, 0.0} : A[(int64_t)i * lda + j];
     std::lock_guard<std::mutex> lock(g_mutex);
-    return lhaf_host_matrix(A0.data(), N, out, diag, prec == GBS_FP32_COMP);
+    return lhaf_host_matrix(A0.data(), N, out, diag, prec);
 }
 
 gbs_status gbs_probability(const gbs_z* Q, const gbs_z* alpha, const int32_t* pattern, int32_t M,
                            gbs_precision prec, double* p_out, gbs_z* lhaf_out, gbs_diag* diag) {
     if (!p_out || (M > 0 && !pattern)) return fail(GBS_E_ARG, "null output or pattern");
-    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP && prec != GBS_DD) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
     std::vector<gbs_z> B((size_t)M * M), gamma(M);
     double pvac = 0.0;
     gbs_status st = gbs_pure_state(Q, alpha, M, B.data(), gamma.data(), &pvac);
@@ -621,7 +673,7 @@ gbs_status gbs_probability(const gbs_z* Q, const gbs_z* alpha, const int32_t* pa
     gbs_z lh{1.0, 0.0};
     {
         std::lock_guard<std::mutex> lock(g_mutex);
-        st = lhaf_host_matrix(Aexp.data(), N, &lh, diag, prec == GBS_FP32_COMP);
+        st = lhaf_host_matrix(Aexp.data(), N, &lh, diag, prec);
     }
     if (st != GBS_OK) return st;
     *p_out = pvac * (lh.re * lh.re + lh.im * lh.im) * std::exp(-lfactorial_sum(pattern, M));
@@ -632,13 +684,15 @@ gbs_status gbs_probability(const gbs_z* Q, const gbs_z* alpha, const int32_t* pa
 gbs_status gbs_lhaf_terms(const gbs_z* A, int32_t N, int64_t lda, const uint64_t* masks, int64_t count,
                           gbs_precision prec, gbs_z* terms_out) {
     if (count < 0 || (count > 0 && (!masks || !terms_out))) return fail(GBS_E_ARG, "bad mask list");
-    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP && prec != GBS_DD) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
     gbs_status st = check_matrix(A, N, lda, "A", true);
     if (st != GBS_OK) return st;
     if (N < 1) return fail(GBS_E_ARG, "terms need N >= 1");
     if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d exceeds %d", N, GBS_MAX_DIM);
     const int Np = N + (N & 1), n = Np / 2;
-    const bool fp32 = prec == GBS_FP32_COMP;
+    const bool fp32 = prec == GBS_FP32_COMP, dd = prec == GBS_DD;
+    if (dd && n > gbs::kMaxDdPairs)
+        return fail(GBS_E_TOO_LARGE, "double-double path: dimension %d exceeds %d", N, 2 * gbs::kMaxDdPairs);
     for (int64_t j = 0; j < count; ++j)
         if (n < 64 && (masks[j] >> n) != 0) return fail(GBS_E_ARG, "mask %lld has bits beyond n = %d", (long long)j, n);
     std::lock_guard<std::mutex> lock(g_mutex);
@@ -674,17 +728,26 @@ gbs_status gbs_lhaf_terms(const gbs_z* A, int32_t N, int64_t lda, const uint64_t
             if (c->terms) hipFree(c->terms);
             c->terms = nullptr;
             HIP_TRY(hipMalloc((void**)&c->terms, sizeof(double2) * len));
-            st = ensure_buffer(&c->E, &c->E_cap, len * 2 * (D + 1) * (fp32 ? sizeof(float2) : sizeof(double2)), 1);
+            const size_t ebytes = dd ? len * 4 * sizeof(double)
+                                     : len * 2 * (D + 1) * (fp32 ? sizeof(float2) : sizeof(double2));
+            st = ensure_buffer(&c->E, &c->E_cap, ebytes, 1);
             if (st != GBS_OK) return st;
             const size_t nblk = (len + 64 * kPerThread - 1) / (64 * kPerThread);
             st = ensure_buffer((void**)&c->partials, &c->partials_cap, nblk * 5, sizeof(double));
             if (st != GBS_OK) return st;
             HIP_TRY(hipMemcpyAsync(c->masks, grp.data() + off, sizeof(uint64_t) * len, hipMemcpyHostToDevice, c->stream));
-            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, c->E, fp32 ? 1 : 0, c->lbmap};
-            HIP_TRY(gbs::launch_charpoly(p1, layout_for(c, n, s), c->stream));
-            gbs::LaunchPhase2 p2{c->E, fp32 ? 1 : 0, len, D, ((n - s) & 1) ? -1.0 : 1.0, kPerThread, c->partials,
-                                 c->terms};
-            HIP_TRY(gbs::launch_series(n, p2, c->stream));
+            const double sign = ((n - s) & 1) ? -1.0 : 1.0;
+            if (dd) {
+                HIP_TRY(gbs::launch_charpoly_dd(c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, sign, c->E,
+                                                c->stream));
+                HIP_TRY(gbs::launch_dd_block_reduce(c->E, len, kPerThread, c->partials, c->terms, c->stream));
+            } else {
+                gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, c->E, fp32 ? 1 : 0,
+                                     c->lbmap};
+                HIP_TRY(gbs::launch_charpoly(p1, layout_for(c, n, s), c->stream));
+                gbs::LaunchPhase2 p2{c->E, fp32 ? 1 : 0, len, D, sign, kPerThread, c->partials, c->terms};
+                HIP_TRY(gbs::launch_series(n, p2, c->stream));
+            }
             std::vector<double2> th(len);
             HIP_TRY(hipMemcpyAsync(th.data(), c->terms, sizeof(double2) * len, hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(hipStreamSynchronize(c->stream));
@@ -700,7 +763,7 @@ gbs_status gbs_lhaf_device(const gbs_z* A_dev, int32_t N, gbs_precision prec, gb
                            void* stream) {
     if (N < 0 || (N > 0 && !A_dev) || !out_dev) return fail(GBS_E_ARG, "bad device arguments");
     if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d exceeds %d", N, GBS_MAX_DIM);
-    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP && prec != GBS_DD) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
     std::lock_guard<std::mutex> lock(g_mutex);
     DevCtx* c = nullptr;
     gbs_status st = current_ctx(&c);
@@ -712,7 +775,7 @@ gbs_status gbs_lhaf_device(const gbs_z* A_dev, int32_t N, gbs_precision prec, gb
     HIP_TRY(hipStreamWaitEvent(s, c->done, 0));
     if (Np > 0)
         HIP_TRY(gbs::launch_prep(reinterpret_cast<const double2*>(A_dev), N, N, Np, c->A0, c->dvec, s));
-    st = run_sum(c, Np, s, reinterpret_cast<double2*>(out_dev), abs_sum_dev, nullptr, prec == GBS_FP32_COMP);
+    st = run_sum(c, Np, s, reinterpret_cast<double2*>(out_dev), abs_sum_dev, nullptr, prec);
     if (st != GBS_OK) return st;
     HIP_TRY(hipEventRecord(c->done, s));
     return GBS_OK;

@@ -223,6 +223,7 @@ extern "C" gbs_status gbs_sample_pure(const gbs_z* Q, const gbs_z* alpha, int32_
     if (!Q || !alpha) return fail(GBS_E_ARG, "null Q or alpha");
     if (nsamples > 0 && (!uniforms || !samples_out || (M > 1 && !normals)))
         return fail(GBS_E_ARG, "null random inputs or output");
+    if (prec == GBS_DD) return fail(GBS_E_UNSUPPORTED, "the sampling chain runs in FP64 or FP32_COMP");
     if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
     if (M > gbs::kMaxSamplerModes) return fail(GBS_E_TOO_LARGE, "%d modes exceed %d", M, gbs::kMaxSamplerModes);
     if (cutoff > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "cutoff %d exceeds %d", cutoff, GBS_MAX_DIM);

@@ -1,0 +1,127 @@
+"""The double-double path (GBS_DD) on the GPU.
+
+Its accuracy is pinned by references that are more accurate than it: exact
+telephone numbers T(n) for all-ones matrices (caption of Fig. 2), and the
+definition evaluated in 50-digit mpmath for random complex matrices.  At the
+benchmark sizes, where no such reference is affordable, it must agree with the
+long-double oracle to the oracle's own accuracy, its subset terms must match
+the oracle's one by one, and a permuted matrix (a different split into subsets,
+so different rounding) must give the same value to double-double accuracy.
+"""
+from fractions import Fraction
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_15595_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gbs():
+    import paper_2010_15595_amd as g
+
+    g.init(0)
+    return g
+
+
+def _dd(gbs, A):
+    v, d = gbs.lhaf(A, prec=gbs.GBS_DD, with_diag=True)
+    lo = d["lhaf_lo"]
+    return v, lo, d
+
+
+# Error bound of the double-double path, normwise like the FP64 one:
+# |lhaf_dd - lhaf| <= DD_TOL * sum_S |t_S|, about 160 units of 2^-106.
+DD_TOL = 2e-30
+
+
+def _exact_rel(hi, lo, ref):
+    """|hi + lo - ref| / |ref| with the double-double value taken exactly."""
+    re = Fraction(hi.real) + Fraction(lo.real)
+    im = Fraction(hi.imag) + Fraction(lo.imag)
+    return float(abs(re - ref) / ref) + float(abs(im) / ref)
+
+
+@pytest.mark.parametrize("n", [2, 7, 12, 16, 21, 24, 30, 36])
+def test_allones_exact_telephone_numbers(gbs, n):
+    hi, lo, d = _dd(gbs, np.ones((n, n), dtype=complex))
+    T = oracle.telephone(n)
+    rel = _exact_rel(hi, lo, T)
+    print(f"[dd all-ones n={n}] rel err {rel:.2e} kappa {d['kappa']:.2e} ({d['kernel_ms']:.1f} ms)", flush=True)
+    assert rel < DD_TOL * max(1.0, d["kappa"])
+
+
+@pytest.mark.parametrize("N,seed", [(5, 1), (10, 2), (14, 3), (16, 4)])
+def test_random_complex_against_mpmath(gbs, N, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    A = (A + A.T) / 2
+    ref = oracle.lhaf_mpmath(A, dps=50, exact=True)
+    hi, lo, d = _dd(gbs, A)
+    with mpmath.workdps(50):
+        got = mpmath.mpc(hi.real, hi.imag) + mpmath.mpc(lo.real, lo.imag)
+        rel = float(abs(got - ref) / abs(ref))
+    print(f"[dd random N={N}] rel err {rel:.2e} kappa {d['kappa']:.2e}", flush=True)
+    assert rel < DD_TOL * max(1.0, d["kappa"])
+
+
+def test_benchmark_family_agrees_with_long_double(gbs):
+    """N = 40 of the benchmark family: the long-double oracle is the less
+    accurate side here; FP64 is far less accurate still."""
+    st = workloads.config3(40)
+    A = gbs.expand(st["B"], st["gamma"], st["pattern"])
+    hi, lo, d = _dd(gbs, A)
+    ld, ab = oracle.lhaf_pt(A, prec="ld", with_abs=True)
+    ld = oracle.to_complex(ld)
+    f64 = gbs.lhaf(A)
+    e_ld = abs(hi - ld) / float(ab)
+    e_64 = abs(hi - f64) / float(ab)
+    print(f"[dd N=40] |dd-ld|/sum|t| = {e_ld:.2e}, |dd-fp64|/sum|t| = {e_64:.2e}, kappa {d['kappa']:.2e}, "
+          f"{d['kernel_ms']:.0f} ms", flush=True)
+    # the long-double oracle's own error (unit roundoff 5.4e-20, about 2000 times below FP64's)
+    assert e_ld < 1e-17
+    assert e_ld < e_64 / 20
+
+    # a permutation changes every subset's rounding but not the value
+    rng = np.random.default_rng(7)
+    p = rng.permutation(40)
+    hp, lp, _ = _dd(gbs, A[np.ix_(p, p)])
+    diff = abs((hp - hi) + (lp - lo)) / float(ab)
+    print(f"[dd N=40] permuted: |diff|/sum|t| = {diff:.2e}", flush=True)
+    assert diff < DD_TOL
+
+
+def test_sampled_terms_at_full_size(gbs):
+    """N = 50: individual subset terms against the long-double oracle."""
+    st = workloads.config3(50)
+    A = gbs.expand(st["B"], st["gamma"], st["pattern"])
+    rng = np.random.default_rng(3)
+    masks = np.array([int(x) for x in rng.integers(1, 1 << 25, size=24)], dtype=np.uint64)
+    got = gbs.lhaf_terms(A, masks, prec=gbs.GBS_DD)
+    ref = np.array(oracle.terms(A, masks, prec="ld"))
+    rel = np.abs(got - ref) / np.abs(ref)
+    print(f"[dd terms N=50] max rel {rel.max():.2e}", flush=True)
+    assert rel.max() < 1e-13
+
+
+def test_probability_and_edges(gbs):
+    st = workloads.pure_state(4, 0.7, 0.3, seed=5)
+    pat = [2, 1, 0, 3]
+    p_dd = gbs.probability(st["Q"], st["alpha_vec"], pat, prec=gbs.GBS_DD)
+    p_ref = oracle.probability(st["Q"], st["alpha_vec"], pat)[0]
+    assert p_dd == pytest.approx(p_ref, rel=1e-12)
+    hi, lo, _ = _dd(gbs, np.zeros((0, 0), dtype=complex))
+    assert hi == 1.0 and lo == 0.0
+    hi, lo, _ = _dd(gbs, np.array([[2.5 - 1j]]))
+    assert abs((hi - (2.5 - 1j)) + lo) < 1e-30
+    with pytest.raises(gbs.GbsError) as e:
+        gbs.lhaf(np.ones((57, 57), dtype=complex), prec=gbs.GBS_DD)
+    assert e.value.code == -4
+    # haf of an odd matrix is 0; of the all-ones 2k x 2k matrix (2k-1)!!
+    assert gbs.haf(np.ones((7, 7), dtype=complex), prec=gbs.GBS_DD) == 0
+    assert gbs.haf(np.ones((12, 12), dtype=complex), prec=gbs.GBS_DD) == pytest.approx(oracle.double_factorial(11),
+                                                                                       rel=1e-15)
