@@ -324,6 +324,43 @@ def fig1_tvd(args, gbs):
                       "modes": rows}), flush=True)
 
 
+def fig2_accuracy(args, gbs):
+    """Fig. 2 of the paper: relative error of the loop hafnian of the n x n
+    all-ones matrix against the telephone number T(n), for the FP64 and the
+    double-double paths, beside the paper's long-double errors."""
+    from fractions import Fraction
+
+    import numpy as np
+
+    import oracle
+
+    paper = {}
+    with open(os.path.join(ROOT, "tests", "golden", "fig2_allones_relerr.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                paper[int(k)] = float(v)
+    gbs.init(0)
+    rows = {}
+    for n in args.fig2_sizes:
+        A = np.ones((n, n), dtype=complex)
+        T = oracle.telephone(n)
+        t0 = time.perf_counter()
+        v64 = gbs.lhaf(A)
+        t64 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        hi, d = gbs.lhaf(A, prec=gbs.GBS_DD, with_diag=True)
+        tdd = time.perf_counter() - t0
+        lo = d["lhaf_lo"]
+        e64 = float(abs(Fraction(v64.real) - T) / T) + abs(v64.imag) / T
+        edd = float(abs(Fraction(hi.real) + Fraction(lo.real) - T) / T) + abs(hi.imag + lo.imag) / T
+        rows[n] = {"fp64_relerr": e64, "dd_relerr": edd, "paper_long_double_relerr": paper.get(n),
+                   "kappa": d["kappa"], "fp64_seconds": t64, "dd_seconds": tdd}
+        log(f"n={n}: {rows[n]}")
+    print(json.dumps({"metric": "relative error of lhaf(all-ones n x n) vs T(n) (Fig. 2)", "sizes": rows}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,7 +378,7 @@ def main():
                     help="print the hash of the kernel sources the traffic figures are tied to")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["n50", "batch", "sampler", "tvd"], default="n50",
+    ap.add_argument("--workload", choices=["n50", "batch", "sampler", "tvd", "fig2"], default="n50",
                     help="batch: 4096 loop hafnians of uneven N in [10, 36] from one 100-mode state, "
                          "one captured graph of persistent launches per step; sampler: samples/s of the "
                          "conditional sampling chain in the Fig. 1 setting; tvd: the Fig. 1 experiment")
@@ -349,6 +386,7 @@ def main():
     ap.add_argument("--sampler-modes", type=int, default=6)
     ap.add_argument("--tvd-unitaries", type=int, default=10)
     ap.add_argument("--tvd-max-photons", type=int, default=14)
+    ap.add_argument("--fig2-sizes", type=int, nargs="+", default=[30, 34, 38, 42, 46, 48, 50])
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--no-plain", action="store_true", help="batch: skip timing the items one at a time")
     args = ap.parse_args()
@@ -390,6 +428,8 @@ def main():
         return bench_sampler(args, gbs)
     if args.workload == "tvd":
         return fig1_tvd(args, gbs)
+    if args.workload == "fig2":
+        return fig2_accuracy(args, gbs)
 
     N = args.N
     st = workload(N)
@@ -448,7 +488,8 @@ def main():
     log(f"lhaf = {val:.12e}, sum|t_S| = {abs_sum:.4e}, kappa = {abs_sum / abs(val):.3e}")
 
     result = {
-        "metric": "loop hafnians/s and subset-terms/s at N=50 complex128; % FP64 vector peak",
+        "metric": "loop hafnians/s and subset-terms/s at N=50 complex128; % FP64 vector peak"
+                  if args.precision == "fp64" else f"loop hafnians/s at N={N}, {args.precision} path",
         "value": lhaf_per_s,
         "unit": "lhaf/s",
         "n_gpus": 1,
@@ -473,12 +514,15 @@ def main():
         "pct_fp64_peak": 100.0 * flops * lhaf_per_s / (FP64_PEAK_TFLOPS * 1e12),
         "roofline": {
             "bound": "alu",
-            "kernel": "charpoly_kernel<P,Q,MR,MC> (gather + Householder Hessenberg + La Budde; 1, 2 or 4 subsets per wavefront)",
+            "kernel": ("charpoly_dd_kernel (one workgroup per subset, double-double; achieved counts FP64-yardstick "
+                       "flops, each dd operation costs 10-30 FP64 instructions)" if args.precision == "dd" else
+                       "charpoly_kernel<P,Q,MR,MC> (gather + Householder Hessenberg + La Budde; 1, 2 or 4 subsets "
+                       "per wavefront)"),
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None,
-            "traffic": traffic_entry(),
+            "traffic": traffic_entry() if args.precision == "fp64" else None,
             "traffic_unit": "HBM bytes per launch of the dominant instance (8x8 lanes, MR = MC = 4)",
             "algorithmic_bytes_per_subset": 2 * (n + 2) * 16,
             "launches_per_step": prof["charpoly_launches"] / args.steps,
