@@ -361,6 +361,33 @@ def fig2_accuracy(args, gbs):
           flush=True)
 
 
+def methods_comparison(args, gbs):
+    """Sec. IV compares La Budde with diagonalisation: the same subset sum on
+    the LDS-resident reference kernels with either method (FP64), beside the
+    production FP64 kernels, each scored against the double-double value."""
+    from paper_2010_15595_amd import workloads
+
+    gbs.init(0)
+    rows = {}
+    for N in args.method_sizes:
+        st = workloads.config3(N)
+        A = gbs.expand(st["B"], st["gamma"], st["pattern"])
+        ref, dref = gbs.lhaf(A, prec=gbs.GBS_DD, with_diag=True)
+        row = {"kappa": dref["kappa"], "dd_kernel_ms": dref["kernel_ms"]}
+        for name, fn in (("production_fp64", lambda: gbs.lhaf(A, with_diag=True)),
+                         ("labudde_lds_fp64", lambda: gbs.lhaf_method(A, gbs.GBS_CHARPOLY_LABUDDE, with_diag=True)),
+                         ("eigen_lds_fp64", lambda: gbs.lhaf_method(A, gbs.GBS_CHARPOLY_EIGEN, with_diag=True))):
+            fn()  # warm
+            v, d = fn()
+            row[name] = {"kernel_ms": d["kernel_ms"], "err_over_sum_abs": abs(v - ref) / dref["abs_sum"],
+                         "rel_err": abs(v - ref) / abs(ref)}
+        row["eigen_over_labudde_time"] = row["eigen_lds_fp64"]["kernel_ms"] / row["labudde_lds_fp64"]["kernel_ms"]
+        rows[N] = row
+        log(f"N={N}: {row}")
+    print(json.dumps({"metric": "La Budde vs eigenvalue characteristic polynomials (Sec. IV)", "sizes": rows}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -378,7 +405,7 @@ def main():
                     help="print the hash of the kernel sources the traffic figures are tied to")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["n50", "batch", "sampler", "tvd", "fig2"], default="n50",
+    ap.add_argument("--workload", choices=["n50", "batch", "sampler", "tvd", "fig2", "methods"], default="n50",
                     help="batch: 4096 loop hafnians of uneven N in [10, 36] from one 100-mode state, "
                          "one captured graph of persistent launches per step; sampler: samples/s of the "
                          "conditional sampling chain in the Fig. 1 setting; tvd: the Fig. 1 experiment")
@@ -386,6 +413,7 @@ def main():
     ap.add_argument("--sampler-modes", type=int, default=6)
     ap.add_argument("--tvd-unitaries", type=int, default=10)
     ap.add_argument("--tvd-max-photons", type=int, default=14)
+    ap.add_argument("--method-sizes", type=int, nargs="+", default=[16, 24, 32, 36, 40])
     ap.add_argument("--fig2-sizes", type=int, nargs="+", default=[30, 34, 38, 42, 46, 48, 50])
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--no-plain", action="store_true", help="batch: skip timing the items one at a time")
@@ -430,6 +458,8 @@ def main():
         return fig1_tvd(args, gbs)
     if args.workload == "fig2":
         return fig2_accuracy(args, gbs)
+    if args.workload == "methods":
+        return methods_comparison(args, gbs)
 
     N = args.N
     st = workload(N)

@@ -126,6 +126,25 @@ gbs_status gbs_lhaf(const gbs_z *A, int32_t M, int64_t lda, const gbs_z *gamma,
 gbs_status gbs_haf(const gbs_z *A, int32_t N, int64_t lda, gbs_precision prec, gbs_z *out,
                    gbs_diag *diag);
 
+/* Characteristic-polynomial method of the reference kernels. */
+typedef enum {
+    GBS_CHARPOLY_LABUDDE = 0, /* La Budde over the Hessenberg form (the paper's method, Sec. IV) */
+    GBS_CHARPOLY_EIGEN = 1    /* eigenvalues of the Hessenberg form by the single-shift complex QR
+                                 algorithm, multiplied out: the diagonalisation the paper compares
+                                 La Budde with (Sec. IV) */
+} gbs_charpoly;
+
+/* lhaf of an N x N symmetric matrix A (leading dim lda, diagonal = loop weights)
+ * on the LDS-resident reference kernels (one workgroup per subset, the same
+ * formulation as gbs_lhaf) with the characteristic polynomials from `method`:
+ * for comparing the two methods in one framework.  prec GBS_FP64 (either
+ * method, N <= 64) or GBS_DD (La Budde only, N <= 56; diag->lhaf_lo holds the
+ * low part); GBS_E_UNSUPPORTED otherwise.  GBS_E_NONFINITE when a subset's QR
+ * iteration needs more than 30 sweeps for one eigenvalue.  Host pointers;
+ * synchronous; diag may be NULL. */
+gbs_status gbs_lhaf_method(const gbs_z *A, int32_t N, int64_t lda, gbs_precision prec, gbs_charpoly method,
+                           gbs_z *out, gbs_diag *diag);
+
 /* Pure-state photon-number probability, Eq. (12):
  *   p(S) = p(vac) |lhaf(filldiag(B_S, gamma_S))|^2 / prod_i s_i!
  * Q: 2M x 2M (row-major, dense), alpha: 2M, pattern: M photon counts >= 0.

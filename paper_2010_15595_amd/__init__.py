@@ -8,6 +8,8 @@ the C ABI of include/gbs_lhaf.h.  This package is the thin Python binding.
 """
 from ._lib import (  # noqa: F401
     BatchPlan,
+    GBS_CHARPOLY_EIGEN,
+    GBS_CHARPOLY_LABUDDE,
     GBS_DD,
     GBS_FP32_COMP,
     GBS_FP64,
@@ -19,6 +21,7 @@ from ._lib import (  # noqa: F401
     init,
     lhaf,
     lhaf_device,
+    lhaf_method,
     lhaf_terms,
     lib,
     max_dim,

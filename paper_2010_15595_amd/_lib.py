@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "libgbs_lhaf.so")
 GBS_FP64 = 0
 GBS_FP32_COMP = 1
 GBS_DD = 2
+GBS_CHARPOLY_LABUDDE = 0
+GBS_CHARPOLY_EIGEN = 1
 
 STATUS = {
     0: "GBS_OK", -1: "GBS_E_ARG", -2: "GBS_E_NOT_SYMMETRIC", -3: "GBS_E_NONFINITE", -4: "GBS_E_TOO_LARGE",
@@ -115,6 +117,9 @@ def lib():
         L.gbs_sample_pure.argtypes = [ZP, ZP, ctypes.c_int32, ctypes.c_int32, DP, DP, ctypes.c_int32, ctypes.c_int,
                                       I32P, DP, ctypes.POINTER(gbs_sample_info)]
         L.gbs_sample_pure.restype = st
+        L.gbs_lhaf_method.argtypes = [ZP, ctypes.c_int32, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ZP,
+                                      ctypes.POINTER(gbs_diag)]
+        L.gbs_lhaf_method.restype = st
         L.gbs_lhaf_terms.argtypes = [ZP, ctypes.c_int32, ctypes.c_int64, U64P, ctypes.c_int64, ctypes.c_int, ZP]
         L.gbs_lhaf_terms.restype = st
         L.gbs_lhaf_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
@@ -213,6 +218,17 @@ def lhaf(A, gamma=None, mult=None, prec=GBS_FP64, with_diag=False):
     d = gbs_diag()
     _check(lib().gbs_lhaf(_zp(A), M, M, _zp(g), mu.ctypes.data_as(I32P) if mu is not None else None, prec,
                           ctypes.byref(out), ctypes.byref(d)))
+    val = complex(out.re, out.im)
+    return (val, _diag_dict(d)) if with_diag else val
+
+
+def lhaf_method(A, method=GBS_CHARPOLY_LABUDDE, prec=GBS_FP64, with_diag=False):
+    """lhaf on the LDS-resident reference kernels with La Budde (method 0) or
+    eigenvalue (method 1) characteristic polynomials."""
+    A = _zarr(A)
+    out = gbs_z()
+    d = gbs_diag()
+    _check(lib().gbs_lhaf_method(_zp(A), A.shape[0], A.shape[0], prec, method, ctypes.byref(out), ctypes.byref(d)))
     val = complex(out.re, out.im)
     return (val, _diag_dict(d)) if with_diag else val
 

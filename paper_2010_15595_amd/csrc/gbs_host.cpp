@@ -236,16 +236,19 @@ gbs_status expand_impl(const gbs_z* B, int32_t M, int64_t ldb, const gbs_z* gamm
 }
 
 // Subset-sum schedule on prepared workspace (ctx->A0, ctx->dvec).
-// Double-double subset sum: per size class and chunk, one workgroup per subset
-// writes its term, a block reduction folds them into dd partials, and one
-// final fixed-order dd reduction gives hi (out_dev) and lo (lo_dev) parts.
-gbs_status run_sum_dd(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double2* lo_dev, double* abs_dev,
-                      int* launches) {
+// Subset sum on the LDS-resident kernels (double-double, or FP64 with either
+// characteristic-polynomial method): per size class and chunk, one workgroup
+// per subset writes its term, a block reduction folds them into dd partials,
+// and one final fixed-order dd reduction gives hi (out_dev) and lo (lo_dev).
+gbs_status run_sum_lds(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double2* lo_dev, double* abs_dev,
+                       int* launches, int prec_dd, int method) {
     const int n = Np / 2, D = n + 1;
-    if (n > gbs::kMaxDdPairs)
-        return fail(GBS_E_TOO_LARGE, "double-double path: dimension %d exceeds %d", Np, 2 * gbs::kMaxDdPairs);
-    constexpr int kDdPer = 8;  // terms per lane in the block reduction
-    const uint64_t per_block = 64ull * kDdPer;
+    const int maxp = gbs::lds_max_pairs(prec_dd, method);
+    if (n > maxp)
+        return fail(GBS_E_TOO_LARGE, "%s path: dimension %d exceeds %d",
+                    prec_dd ? "double-double" : "LDS", Np, 2 * maxp);
+    constexpr int kLdsPer = 8;  // terms per lane in the block reduction
+    const uint64_t per_block = 64ull * kLdsPer;
     uint64_t max_len = 0, total_blocks = 0;
     for (int s = 1; s <= n; ++s) {
         const uint64_t cnt = binom_host(n, s);
@@ -255,7 +258,7 @@ gbs_status run_sum_dd(DevCtx* c, int Np, hipStream_t st, double2* out_dev, doubl
             total_blocks += (len + per_block - 1) / per_block;
         }
     }
-    gbs_status s1 = ensure_buffer(&c->E, &c->E_cap, (size_t)max_len * 4 * sizeof(double), 1);
+    gbs_status s1 = ensure_buffer(&c->E, &c->E_cap, (size_t)max_len * gbs::lds_term_bytes(prec_dd), 1);
     if (s1 != GBS_OK) return s1;
     s1 = ensure_buffer((void**)&c->partials, &c->partials_cap, (size_t)total_blocks * 5, sizeof(double));
     if (s1 != GBS_OK) return s1;
@@ -267,10 +270,11 @@ gbs_status run_sum_dd(DevCtx* c, int Np, hipStream_t st, double2* out_dev, doubl
         for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
             const uint64_t len = std::min(kChunk, cnt - st0);
             HIP_TRY(timed_launch(kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st, [&] {
-                return gbs::launch_charpoly_dd(c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, sign, c->E, st);
+                return gbs::launch_charpoly_lds(prec_dd, method, c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D,
+                                                sign, c->E, st);
             }));
             HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, st, [&] {
-                return gbs::launch_dd_block_reduce(c->E, len, kDdPer, c->partials + 5 * poff, nullptr, st);
+                return gbs::launch_lds_block_reduce(prec_dd, c->E, len, kLdsPer, c->partials + 5 * poff, nullptr, st);
             }));
             poff += (len + per_block - 1) / per_block;
             nl += 2;
@@ -283,8 +287,9 @@ gbs_status run_sum_dd(DevCtx* c, int Np, hipStream_t st, double2* out_dev, doubl
     return GBS_OK;
 }
 
+// lds_method >= 0 selects the LDS-resident kernels with that characteristic-polynomial method.
 gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* abs_dev, int* launches,
-                   gbs_precision prec, double2* lo_dev = nullptr) {
+                   gbs_precision prec, double2* lo_dev = nullptr, int lds_method = -1) {
     const int n = Np / 2;
     int nl = 0;
     if (n == 0) {
@@ -293,7 +298,9 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
         if (launches) *launches = 1;
         return GBS_OK;
     }
-    if (prec == GBS_DD) return run_sum_dd(c, Np, st, out_dev, lo_dev, abs_dev, launches);
+    if (prec == GBS_DD || lds_method >= 0)
+        return run_sum_lds(c, Np, st, out_dev, lo_dev, abs_dev, launches, prec == GBS_DD ? 1 : 0,
+                           lds_method >= 0 ? lds_method : gbs::kCharpolyLaBudde);
     if (lo_dev) HIP_TRY(gbs::launch_scalar_set(lo_dev, make_double2(0.0, 0.0), nullptr, 0.0, st));
     const bool fp32 = prec == GBS_FP32_COMP;
     const int D = n + 1;
@@ -336,7 +343,8 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
 }
 
 // Full evaluation of an expanded host matrix (N x N, diagonal = loop weights).
-gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* diag, gbs_precision prec) {
+gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* diag, gbs_precision prec,
+                            int lds_method = -1) {
     DevCtx* c = nullptr;
     gbs_status st = current_ctx(&c);
     if (st != GBS_OK) return st;
@@ -348,7 +356,8 @@ gbs_status lhaf_host_matrix(const gbs_z* A, int32_t N, gbs_z* out, gbs_diag* dia
     HIP_TRY(hipEventRecord(c->t0, c->stream));
     if (Np > 0) HIP_TRY(gbs::launch_prep(c->Ain, N, N, Np, c->A0, c->dvec, c->stream));
     int launches = 0;
-    st = run_sum(c, Np, c->stream, c->res, reinterpret_cast<double*>(c->res + 1), &launches, prec, c->res + 2);
+    st = run_sum(c, Np, c->stream, c->res, reinterpret_cast<double*>(c->res + 1), &launches, prec, c->res + 2,
+                 lds_method);
     if (st != GBS_OK) return st;
     HIP_TRY(hipEventRecord(c->t1, c->stream));
     double2 h[3];
@@ -656,6 +665,32 @@ gbs_status gbs_haf(const gbs_z* A, int32_t N, int64_t lda, gbs_precision prec, g
         for (int j = 0; j < N; ++j) A0[(size_t)i * N + j] = (i == j) ? gbs_z{0.0, 0.0} : A[(int64_t)i * lda + j];
     std::lock_guard<std::mutex> lock(g_mutex);
     return lhaf_host_matrix(A0.data(), N, out, diag, prec);
+}
+
+gbs_status gbs_lhaf_method(const gbs_z* A, int32_t N, int64_t lda, gbs_precision prec, gbs_charpoly method,
+                           gbs_z* out, gbs_diag* diag) {
+    if (!out) return fail(GBS_E_ARG, "null output");
+    if (method != GBS_CHARPOLY_LABUDDE && method != GBS_CHARPOLY_EIGEN) return fail(GBS_E_ARG, "bad method %d", (int)method);
+    if (prec == GBS_FP32_COMP || (prec == GBS_DD && method == GBS_CHARPOLY_EIGEN))
+        return fail(GBS_E_UNSUPPORTED, "the reference kernels run La Budde in FP64 or double-double, eigenvalues in FP64");
+    if (prec != GBS_FP64 && prec != GBS_DD) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    gbs_status st = check_matrix(A, N, lda, "A", true);
+    if (st != GBS_OK) return st;
+    if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d exceeds %d", N, GBS_MAX_DIM);
+    std::vector<gbs_z> Ah((size_t)N * N);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) Ah[(size_t)i * N + j] = A[(int64_t)i * lda + j];
+    gbs_z v{0.0, 0.0};
+    {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        st = lhaf_host_matrix(Ah.data(), N, &v, diag, prec,
+                              method == GBS_CHARPOLY_EIGEN ? gbs::kCharpolyEigen : gbs::kCharpolyLaBudde);
+    }
+    if (st != GBS_OK) return st;
+    if (!std::isfinite(v.re) || !std::isfinite(v.im))
+        return fail(GBS_E_NONFINITE, "a subset's QR iteration did not converge (or the result overflowed)");
+    *out = v;
+    return GBS_OK;
 }
 
 gbs_status gbs_probability(const gbs_z* Q, const gbs_z* alpha, const int32_t* pattern, int32_t M,

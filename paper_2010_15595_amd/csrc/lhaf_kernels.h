@@ -89,16 +89,27 @@ hipError_t launch_batch_prep(const double2* mats, const int64_t* in_off, const i
                              hipStream_t st);
 hipError_t launch_fill_u32(unsigned* p, int count, hipStream_t st);
 
-// ---- double-double subset terms (extended precision path) ----
-constexpr int kMaxDdPairs = 28;  // N <= 56: the (m+1)^2 matrix and the La Budde ring fit in LDS
+// ---- subset terms with the matrix in LDS (double-double path, method comparison) ----
+enum { kCharpolyLaBudde = 0, kCharpolyEigen = 1 };
+constexpr int kMaxDdPairs = 28;  // N <= 56: the (m+1)^2 matrix and the La Budde ring fit in LDS in double-double
 size_t dd_lds_bytes(int m, int D);
-// One workgroup per subset of size s; terms (count double-double complex
-// values, 32 bytes each) receive the signed subset terms.
+size_t lds_bytes(int m, int D, int prec_dd, int method);
+// Largest n for the arithmetic / method (0 = unsupported pair).
+int lds_max_pairs(int prec_dd, int method);
+// Bytes per subset term in the terms buffer (32 double-double, 16 FP64).
+size_t lds_term_bytes(int prec_dd);
+// One workgroup per subset of size s; terms receive the signed subset terms
+// (NaN for a subset whose QR iteration did not converge).
+hipError_t launch_charpoly_lds(int prec_dd, int method, const double2* A0, const double2* dvec, int Np, int s,
+                               uint64_t rank0, uint64_t count, const uint64_t* masks, const uint64_t* binom, int D,
+                               double sign, void* terms, hipStream_t st);
 hipError_t launch_charpoly_dd(const double2* A0, const double2* dvec, int Np, int s, uint64_t rank0, uint64_t count,
                               const uint64_t* masks, const uint64_t* binom, int D, double sign, void* terms,
                               hipStream_t st);
-// Fixed-order sums: blocks of 64 * per terms into partials (5 doubles: re.hi,
-// re.lo, im.hi, im.lo, sum |t|), optionally the terms rounded to double.
+// Fixed-order double-double sums: blocks of 64 * per terms into partials (5
+// doubles: re.hi, re.lo, im.hi, im.lo, sum |t|), optionally the terms rounded to double.
+hipError_t launch_lds_block_reduce(int prec_dd, const void* terms, uint64_t count, int per, double* partials,
+                                   double2* terms_out, hipStream_t st);
 hipError_t launch_dd_block_reduce(const void* terms, uint64_t count, int per, double* partials, double2* terms_out,
                                   hipStream_t st);
 hipError_t launch_dd_final_reduce(const double* partials, int64_t np, double2* out_hi, double2* out_lo, double* abs_out,

@@ -166,3 +166,21 @@ def test_sample_pure_validation():
     _expect(-5, gbs.sample_pure, mixed, al, 4, z, u)
     big = workloads.pure_state(129, 0.1, 0.1, seed=1)
     _expect(-4, gbs.sample_pure, big["Q"], big["alpha_vec"], 2, np.zeros((1, 256)), np.zeros((1, 129)))
+
+
+def test_double_double_is_single_evaluation_only():
+    """GBS_DD is refused by batch plans and the sampler before any device work."""
+    code = gbs.lib().gbs_batch_plan_create((ctypes.c_int32 * 1)(10), 1, gbs.GBS_DD, 0, ctypes.byref(ctypes.c_void_p()))
+    assert code == -9
+    st = workloads.pure_state(2, 0.5, 0.2, seed=1)
+    _expect(-9, gbs.sample_pure, st["Q"], st["alpha_vec"], 3, np.zeros((1, 2)), np.zeros((1, 2)), gbs.GBS_DD)
+
+
+def test_method_entry_validation():
+    A = np.eye(4, dtype=complex)
+    _expect(-9, gbs.lhaf_method, A, gbs.GBS_CHARPOLY_EIGEN, gbs.GBS_DD)
+    _expect(-9, gbs.lhaf_method, A, gbs.GBS_CHARPOLY_LABUDDE, gbs.GBS_FP32_COMP)
+    _expect(-1, gbs.lhaf_method, A, 7)
+    B = A.copy()
+    B[0, 1] = 1.0
+    _expect(-2, gbs.lhaf_method, B, gbs.GBS_CHARPOLY_LABUDDE)

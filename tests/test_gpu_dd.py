@@ -125,3 +125,22 @@ def test_probability_and_edges(gbs):
     assert gbs.haf(np.ones((7, 7), dtype=complex), prec=gbs.GBS_DD) == 0
     assert gbs.haf(np.ones((12, 12), dtype=complex), prec=gbs.GBS_DD) == pytest.approx(oracle.double_factorial(11),
                                                                                        rel=1e-15)
+
+
+def test_mixed_state_probability(gbs):
+    """Eq. (11) with the double-double path: a noisy 3-mode state whose 2N x 2N
+    loop hafnian cancels heavily; the long-double oracle is the reference and
+    the double-double result must sit within its accuracy, far closer than FP64."""
+    st = workloads.pure_state(3, 0.8, 0.3, seed=2)
+    Q = st["Q"] + 0.15 * np.eye(6)
+    pat = [3, 2, 3]  # 8 photons: a 16 x 16 loop hafnian
+    p_dd, lh_dd, d = gbs.probability_mixed(Q, st["alpha_vec"], pat, prec=gbs.GBS_DD, with_lhaf=True,
+                                           with_diag=True)
+    p64, lh64 = gbs.probability_mixed(Q, st["alpha_vec"], pat, with_lhaf=True)
+    _, lh_ref = oracle.probability_mixed(Q, st["alpha_vec"], pat)
+    lh_ref = complex(lh_ref)
+    e_dd = abs(lh_dd - lh_ref) / d["abs_sum"]
+    e_64 = abs(lh64 - lh_ref) / d["abs_sum"]
+    print(f"[dd mixed] kappa {d['kappa']:.2e}: |dd-ld|/sum|t| {e_dd:.2e}, |fp64-ld|/sum|t| {e_64:.2e}", flush=True)
+    assert e_dd < 1e-17
+    assert p_dd > 0
