@@ -88,9 +88,17 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
         double cost;
         int round;
     };
+    // items with n <= small_pairs pairs are summed whole by one wavefront each
+    // (GBS_SMALL_PAIRS overrides the default kSmallPairs; 0 disables)
+    int small_pairs = gbs::kSmallPairs;
+    if (const char* e = std::getenv("GBS_SMALL_PAIRS")) small_pairs = std::max(0, std::min(gbs::kSmallPairs, atoi(e)));
     std::vector<HostTile> ht;
     for (int i = 0; i < nitems; ++i) {
         const int n = S.npair[i];
+        if (!fp32 && n >= 1 && n <= small_pairs) {
+            S.small.push_back(i);
+            continue;
+        }
         for (int s = 1; s <= n; ++s) {
             const uint64_t cnt = binom_host(n, s);
             const int lay = layout_for(c, n, s);
@@ -108,6 +116,7 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
             }
         }
     }
+    std::stable_sort(S.small.begin(), S.small.end(), [&](int a, int b) { return S.npair[a] > S.npair[b]; });
     // partials: per item contiguous, in (item, s, rank) order
     S.pbeg.assign(nitems + 1, 0);
     std::vector<int64_t> tile_pidx(ht.size());
@@ -188,6 +197,15 @@ gbs_status batch_enqueue(DevCtx* c, const BatchSchedule& S, const BatchDev& d, h
     hipEvent_t ev_prep;
     HIP_TRY(new_event(&ev_prep));
     HIP_TRY(hipEventRecord(ev_prep, cs));
+    hipEvent_t ev_small = nullptr;
+    if (!S.small.empty()) {
+        hipStream_t bs = br[kBatchBranches - 1];
+        HIP_TRY(hipStreamWaitEvent(bs, ev_prep, 0));
+        HIP_TRY(gbs::launch_small_items(d.small, (int)S.small.size(), d.items, c->binom, c->lbmap, d.out, d.abs,
+                                        kPersistentWaves, bs));
+        HIP_TRY(new_event(&ev_small));
+        HIP_TRY(hipEventRecord(ev_small, bs));
+    }
     std::vector<hipEvent_t> ev_series(S.rounds, nullptr);
     size_t ci = 0, si = 0;
     for (int r = 0; r < S.rounds; ++r) {
@@ -217,7 +235,8 @@ gbs_status batch_enqueue(DevCtx* c, const BatchSchedule& S, const BatchDev& d, h
         HIP_TRY(new_event(&ev_series[r]));
         HIP_TRY(hipEventRecord(ev_series[r], cs));
     }
-    HIP_TRY(gbs::launch_item_reduce(d.pbeg, nitems, d.partials, d.out, d.abs, cs));
+    if (ev_small) HIP_TRY(hipStreamWaitEvent(cs, ev_small, 0));
+    HIP_TRY(gbs::launch_item_reduce(d.pbeg, nitems, d.partials, d.items, d.out, d.abs, cs));
     return GBS_OK;
 }
 
@@ -254,8 +273,8 @@ void plan_free(gbs_plan* p) {
         if (s) hipStreamDestroy(s);
     if (p->cs) hipStreamDestroy(p->cs);
     const BatchDev& d = p->d;
-    void* bufs[] = {p->staging, d.a0,       d.dv,       d.items,   d.in_off, d.dims,  d.tiles, d.sblocks,
-                    d.pbeg,     d.partials, d.counters, d.ebuf[0], d.ebuf[1], d.out,  d.abs};
+    void* bufs[] = {p->staging, d.a0,       d.dv,       d.items,   d.in_off,  d.dims, d.tiles, d.sblocks,
+                    d.pbeg,     d.partials, d.counters, d.ebuf[0], d.ebuf[1], d.out,  d.abs,   d.small};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete p;
@@ -289,6 +308,7 @@ gbs_status plan_build_into(DevCtx* c, const std::vector<int>& dims, bool fp32, i
     if ((st = upload(&d.tiles, S.tiles, &B)) != GBS_OK) return st;
     if ((st = upload(&d.sblocks, S.sblocks, &B)) != GBS_OK) return st;
     if ((st = upload(&d.pbeg, S.pbeg, &B)) != GBS_OK) return st;
+    if ((st = upload(&d.small, S.small, &B)) != GBS_OK) return st;
     if ((st = dmalloc((void**)&d.partials, sizeof(double) * 5 * (size_t)std::max<int64_t>(1, S.pbeg[nitems]), &B)) !=
         GBS_OK)
         return st;
@@ -392,10 +412,11 @@ gbs_status runner_run(BatchRunner* r, const BatchSchedule& S, const double2* mat
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t n_items = sizeof(gbs::BatchItem) * S.count, n_inoff = sizeof(int64_t) * S.in_off.size(),
                  n_dims = sizeof(int) * S.dims.size(), n_tiles = sizeof(gbs::BatchTile) * S.tiles.size(),
-                 n_sb = sizeof(gbs::SeriesBlock) * S.sblocks.size(), n_pbeg = sizeof(int64_t) * S.pbeg.size();
+                 n_sb = sizeof(gbs::SeriesBlock) * S.sblocks.size(), n_pbeg = sizeof(int64_t) * S.pbeg.size(),
+                 n_small = sizeof(int) * S.small.size();
     const size_t o_items = 0, o_inoff = align(o_items + n_items), o_dims = align(o_inoff + n_inoff),
                  o_tiles = align(o_dims + n_dims), o_sb = align(o_tiles + n_tiles), o_pbeg = align(o_sb + n_sb),
-                 total = align(o_pbeg + n_pbeg);
+                 o_small = align(o_pbeg + n_pbeg), total = align(o_small + n_small);
     const size_t npart = 5 * (size_t)std::max<int64_t>(1, S.pbeg[S.count]);
     const bool grow = r->meta_cap < total || r->a0_cap < sizeof(double2) * (size_t)S.a0_elems ||
                       r->dv_cap < sizeof(double2) * (size_t)S.d_elems || r->partials_cap < sizeof(double) * npart ||
@@ -435,6 +456,7 @@ gbs_status runner_run(BatchRunner* r, const BatchSchedule& S, const double2* mat
     if (n_tiles) std::memcpy(h + o_tiles, S.tiles.data(), n_tiles);
     if (n_sb) std::memcpy(h + o_sb, S.sblocks.data(), n_sb);
     std::memcpy(h + o_pbeg, S.pbeg.data(), n_pbeg);
+    if (n_small) std::memcpy(h + o_small, S.small.data(), n_small);
     HIP_TRY(hipMemcpyAsync(r->meta, h, total, hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(r->upload_done, st));
     r->uploaded = true;
@@ -450,6 +472,7 @@ gbs_status runner_run(BatchRunner* r, const BatchSchedule& S, const double2* mat
     d.tiles = (gbs::BatchTile*)(m + o_tiles);
     d.sblocks = (gbs::SeriesBlock*)(m + o_sb);
     d.pbeg = (int64_t*)(m + o_pbeg);
+    d.small = (int*)(m + o_small);
     d.partials = (double*)r->partials;
     d.counters = (unsigned*)r->counters;
     d.ebuf[0] = r->ebuf[0];

@@ -113,6 +113,7 @@ struct BatchSchedule {
     std::vector<int64_t> pbeg;          // partial records of item i: [pbeg[i], pbeg[i+1])
     std::vector<CharpolyLaunch> cp;
     std::vector<SeriesLaunch> se;
+    std::vector<int> small;             // FP64 items with 1 <= n <= kSmallPairs, largest n first: one wavefront each
 };
 void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, int64_t tile_subsets,
                     int64_t round_bytes, BatchSchedule& S);
@@ -132,6 +133,7 @@ struct BatchDev {
     void* ebuf[2] = {nullptr, nullptr};
     double2* out = nullptr;
     double* abs = nullptr;
+    int* small = nullptr;
 };
 constexpr int kBatchBranches = 4;  // parallel streams of the per-subset launches of one round
 // Issues the whole schedule: counter fill, prep, rounds of per-subset launches

@@ -83,8 +83,15 @@ void lb_fill_table(int4* out);
 hipError_t launch_series_batch(int n, int fp32, const SeriesBlock* blocks, int nblocks, const BatchTile* tiles,
                                const BatchItem* items, const void* Ebase, int per_thread, double* partials,
                                hipStream_t st);
-hipError_t launch_item_reduce(const int64_t* pbeg, int nitems, const double* partials, double2* out, double* abs_out,
-                              hipStream_t st);
+// Per-item fixed-order reduction of the partials; items with pairs but no
+// partials (summed by launch_small_items) are left alone.
+hipError_t launch_item_reduce(const int64_t* pbeg, int nitems, const double* partials, const BatchItem* items,
+                              double2* out, double* abs_out, hipStream_t st);
+// Whole loop hafnians of 1 <= n <= kSmallPairs pairs, one wavefront each
+// (FP64): list holds the item indices, largest n first.
+constexpr int kSmallPairs = 8;
+hipError_t launch_small_items(const int* list, int count, const BatchItem* items, const uint64_t* binom,
+                              const int4* lbmap, double2* out, double* abs_out, int grid, hipStream_t st);
 hipError_t launch_batch_prep(const double2* mats, const int64_t* in_off, const int* N, BatchItem* items, int nitems,
                              hipStream_t st);
 hipError_t launch_fill_u32(unsigned* p, int count, hipStream_t st);

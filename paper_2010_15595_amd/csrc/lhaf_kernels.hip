@@ -246,9 +246,12 @@ __global__ void __launch_bounds__(64) series_batch_kernel(const SeriesBlock* __r
 // Per-item fixed-order reduction of partials [pbeg[i], pbeg[i+1]).
 __global__ void __launch_bounds__(64) item_reduce_kernel(const int64_t* __restrict__ pbeg,
                                                          const double* __restrict__ partials,
+                                                         const BatchItem* __restrict__ items,
                                                          double2* __restrict__ out, double* __restrict__ abs_out) {
     const int i = blockIdx.x;
     const int lane = threadIdx.x;
+    // items with pairs but no partials are summed whole by small_items_kernel
+    if (pbeg[i + 1] == pbeg[i] && items[i].n > 0) return;
     Acc A{0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t k = pbeg[i] + lane; k < pbeg[i + 1]; k += 64) {
         Acc B{partials[5 * k], partials[5 * k + 1], partials[5 * k + 2], partials[5 * k + 3], partials[5 * k + 4]};
@@ -517,10 +520,139 @@ hipError_t launch_series_batch(int n, int fp32, const SeriesBlock* blocks, int n
     return series_batch_dispatch<1>(n, fp32, blocks, nblocks, tiles, Ebase, per_thread, partials, st);
 }
 
-hipError_t launch_item_reduce(const int64_t* pbeg, int nitems, const double* partials, double2* out, double* abs_out,
-                              hipStream_t st) {
+// ---------------------------------------------------------------- small items
+
+namespace {
+
+// Series of one subset for n <= kSmallPairs pairs given at run time: the loops
+// are unrolled to kSmallPairs and guarded, so every array index is constant.
+__device__ __forceinline__ double2 series_term_small(const double2* __restrict__ E, int n, int RS, double sign) {
+    constexpr int NM = kSmallPairs;
+    double2 R[NM + 2], c[NM + 1], Lk[NM + 1], p[NM + 1], e[NM + 1];
+#pragma unroll
+    for (int k = 0; k <= NM + 1; ++k) R[k] = (k <= n + 1) ? E[k] : cz();
+    Lk[0] = cz();
+    p[0] = cz();
+    c[0] = cz();
+#pragma unroll
+    for (int k = 1; k <= NM; ++k) {
+        if (k <= n) {
+            const double2 rp = E[RS + k + 1];
+            double2 acc = make_double2(R[k + 1].x - rp.x, R[k + 1].y - rp.y);
+#pragma unroll
+            for (int j = 1; j < k; ++j) acc = cfms(R[j], Lk[k - j], acc);
+            Lk[k] = acc;
+            double2 pk = make_double2(-(double)k * R[k].x, -(double)k * R[k].y);
+#pragma unroll
+            for (int j = 1; j < k; ++j) pk = cfms(R[j], p[k - j], pk);
+            p[k] = pk;
+            const double hk = 0.5 / (double)k;
+            c[k] = make_double2(fma(pk.x, hk, 0.5 * acc.x), fma(pk.y, hk, 0.5 * acc.y));
+        } else {
+            Lk[k] = p[k] = c[k] = cz();
+        }
+    }
+    e[0] = make_double2(1.0, 0.0);
+    double2 res = cz();
+#pragma unroll
+    for (int k = 1; k <= NM; ++k) {
+        double2 acc = cz();
+#pragma unroll
+        for (int j = 1; j <= k; ++j) acc = cfms(make_double2(-(double)j * c[j].x, -(double)j * c[j].y), e[k - j], acc);
+        const double ik = 1.0 / (double)k;
+        e[k] = make_double2(acc.x * ik, acc.y * ik);
+        if (k == n) res = make_double2(e[k].x * sign, e[k].y * sign);
+    }
+    return res;
+}
+
+// One wavefront per loop hafnian with 1 <= n <= kSmallPairs pairs: all its
+// subsets in groups of four (4x4 lane grid, the register tile of the subset
+// size), each group's series on four lanes, per-lane TwoSum, then a fixed-order
+// merge.  Items are taken from `list` (largest first) with a grid stride.
+__global__ void __launch_bounds__(64) small_items_kernel(const int* __restrict__ list, int count,
+                                                         const BatchItem* __restrict__ items,
+                                                         const uint64_t* __restrict__ binom,
+                                                         const int4* __restrict__ lbmap, double2* __restrict__ out,
+                                                         double* __restrict__ abs_out) {
+    extern __shared__ double2 lds[];
+    constexpr int W = 4;
+    const int lane = threadIdx.x;
+    double2* E = lds + charpoly_lds_bytes(W, 16, kSmallPairs + 1, sizeof(double2)) / sizeof(double2);
+    for (int w = blockIdx.x; w < count; w += gridDim.x) {
+        const int i = __builtin_amdgcn_readfirstlane(list[w]);
+        const BatchItem it = items[i];
+        const int n = it.n, D = n + 1, RS = D + 1;
+        const int4* lbm = lbmap + lb_table_offset(16, D);
+        Acc A{0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int s = 1; s <= n; ++s) {
+            const uint64_t cnt = binom[n * kBinomStride + s];
+            const double sign = ((n - s) & 1) ? -1.0 : 1.0;
+            const int mr = (2 * s + 3) / 4;
+            for (uint64_t first = 0; first < cnt; first += W) {
+                switch (mr) {
+                    case 1:
+                        charpoly_wave<4, 4, 1, 1, double2, 16>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
+                                                               binom, D, lbm, E, lds);
+                        break;
+                    case 2:
+                        charpoly_wave<4, 4, 2, 2, double2, 16>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
+                                                               binom, D, lbm, E, lds);
+                        break;
+                    case 3:
+                        charpoly_wave<4, 4, 3, 3, double2, 16>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
+                                                               binom, D, lbm, E, lds);
+                        break;
+                    default:
+                        charpoly_wave<4, 4, 4, 4, double2, 16>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
+                                                               binom, D, lbm, E, lds);
+                        break;
+                }
+                wave_sync();
+                if (lane < W && first + lane < cnt) acc_add(A, series_term_small(E + lane * 2 * RS, n, RS, sign));
+                wave_sync();
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            Acc B;
+            B.sr = shfl_xor_d(A.sr, off);
+            B.cr = shfl_xor_d(A.cr, off);
+            B.si = shfl_xor_d(A.si, off);
+            B.ci = shfl_xor_d(A.ci, off);
+            B.ab = shfl_xor_d(A.ab, off);
+            if (lane & off) {
+                Acc T = B;
+                acc_merge(T, A);
+                A = T;
+            } else {
+                acc_merge(A, B);
+            }
+        }
+        if (lane == 0) {
+            out[i] = make_double2(A.sr + A.cr, A.si + A.ci);
+            if (abs_out) abs_out[i] = A.ab;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_small_items(const int* list, int count, const BatchItem* items, const uint64_t* binom,
+                              const int4* lbmap, double2* out, double* abs_out, int grid, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    static_assert(kSmallPairs + 2 <= 16, "the 16-lane La Budde team must hold D + 1 coefficients");
+    const size_t lds = charpoly_lds_bytes(4, 16, kSmallPairs + 1, sizeof(double2)) +
+                       sizeof(double2) * 4 * 2 * (kSmallPairs + 2);
+    hipLaunchKernelGGL(small_items_kernel, dim3(std::max(1, std::min(grid, count))), dim3(64), lds, st, list, count,
+                       items, binom, lbmap, out, abs_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_reduce(const int64_t* pbeg, int nitems, const double* partials, const BatchItem* items,
+                              double2* out, double* abs_out, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(item_reduce_kernel, dim3(nitems), dim3(64), 0, st, pbeg, partials, out, abs_out);
+    hipLaunchKernelGGL(item_reduce_kernel, dim3(nitems), dim3(64), 0, st, pbeg, partials, items, out, abs_out);
     return hipGetLastError();
 }
 
