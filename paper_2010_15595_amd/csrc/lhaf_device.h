@@ -373,13 +373,32 @@ __device__ __forceinline__ float swap_sum32(float x) {
 }
 
 struct Lds {
-    double2* vbuf;   // [W][64]: source column of the current reflector
+    double2* vbuf;   // [W][64]: source column of the current reflector (Hessenberg phase)
     double2* misc;   // [W][2]: squared norm, alpha (border subdiagonal)
-    int* idx;        // [W][64]: vertex indices of the subset
-    double2* rowbuf; // [NT][64]: current row of H' (La Budde)
-    void* betab;     // [NT][64]: beta_k of the current row (La Budde type)
+    int* idx;        // [W][64]: vertex indices of the subset (gather phase)
+    double2* rowbuf; // [NT][RB]: current row of H' (La Budde)
+    void* betab;     // [NT][D + 1]: beta_k of the current row (La Budde type)
     void* ring;      // [NT][RS * RS]: last RS trailing characteristic polynomials (anti-diagonal rows)
 };
+
+// Row-buffer length per La Budde team: the register tile of a row spans at
+// most m + Q - 1 <= 2D + 5 entries (m <= 2n = 2D - 2, Q <= 8).
+__host__ __device__ constexpr int lds_rowbuf_len(int D) { return (2 * D + 9 >= 64) ? 64 : ((2 * D + 9) & ~3); }
+
+// Per-wave LDS layout in bytes: misc, rowbuf, betab, then one region that the
+// gather / Hessenberg phase uses for vbuf and idx and La Budde then reuses for
+// the ring (the phases are separated by a wave-level fence).
+struct LdsLayout {
+    size_t rowbuf, betab, region, total;
+};
+__host__ __device__ constexpr LdsLayout lds_layout(int W, int T, int D, int vbytes) {
+    const size_t NT = (size_t)(64 / T), RS = (size_t)(D + 1);
+    const size_t rowbuf = (size_t)16 * W * 2;
+    const size_t betab = rowbuf + (size_t)16 * NT * lds_rowbuf_len(D);
+    const size_t region = (betab + (size_t)vbytes * NT * RS + 15) & ~(size_t)15;
+    const size_t ring_b = (size_t)vbytes * NT * RS * RS, hess_b = (size_t)(16 + 4) * W * 64;
+    return LdsLayout{rowbuf, betab, region, (region + (ring_b > hess_b ? ring_b : hess_b) + 15) & ~(size_t)15};
+}
 
 // La Budde team layout: teams of T lanes (P Q, or 64 when a subset needs more
 // than P Q coefficient lanes).  Within a team, coefficient d gets a group of
@@ -399,7 +418,7 @@ __host__ __device__ constexpr int lb_table_offset(int T, int D) {
 // LDS bytes of the per-subset kernel with teams of T lanes (64 / T teams);
 // vbytes = size of the La Budde complex type.  Non-decreasing in D.
 __host__ __device__ constexpr size_t charpoly_lds_bytes(int W, int T, int D, int vbytes) {
-    return (size_t)16 * (W * (64 + 2 + 16) + (64 / T) * 64) + (size_t)vbytes * (64 / T) * (64 + (D + 1) * (D + 1));
+    return lds_layout(W, T, D, vbytes).total;
 }
 
 template <int P, int Q, int MR, int MC, int KJ>
@@ -584,12 +603,15 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     constexpr int NT = 64 / T;
     const int RS = D + 1;
     Lds L;
-    L.vbuf = lds;
-    L.misc = lds + W * 64;
-    L.idx = reinterpret_cast<int*>(lds + W * 66);
-    L.rowbuf = lds + W * 82;
-    L.betab = L.rowbuf + NT * 64;
-    L.ring = reinterpret_cast<V*>(L.betab) + NT * 64;
+    const LdsLayout ly = lds_layout(W, T, D, (int)sizeof(V));
+    const int RB = lds_rowbuf_len(D);
+    char* lbase = reinterpret_cast<char*>(lds);
+    L.misc = lds;
+    L.rowbuf = reinterpret_cast<double2*>(lbase + ly.rowbuf);
+    L.betab = lbase + ly.betab;
+    L.ring = lbase + ly.region;
+    L.vbuf = reinterpret_cast<double2*>(lbase + ly.region);
+    L.idx = reinterpret_cast<int*>(lbase + ly.region + (size_t)16 * W * 64);
     double2* vb = L.vbuf + g * 64;
     double2* nb = L.misc + g * 2;
     int* idx = L.idx + g * 64;
@@ -685,6 +707,8 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
 
     // Householder reduction of the C block
     hess_all<P, Q, MR, MC, 0>(a, y, m, pr, pc, vb, nb);
+    // vbuf and idx are dead from here on; the La Budde ring reuses their space
+    wave_sync();
 
     // La Budde over the trailing blocks of H' (size m + 1).  Team t of T lanes
     // handles group t + NT * pass; lane d of the team holds coefficient d.
@@ -699,9 +723,9 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     for (int pass = 0; pass < W / NT; ++pass) {
         const int gt = pass * NT + team;          // group served by my team
         const bool own = (g / NT) == pass;        // my group's rows are read this pass
-        double2* rowbuf_own = L.rowbuf + (g % NT) * 64;
-        double2* rowbuf = L.rowbuf + team * 64;
-        V* betab = reinterpret_cast<V*>(L.betab) + team * 64;
+        double2* rowbuf_own = L.rowbuf + (g % NT) * RB;
+        double2* rowbuf = L.rowbuf + team * RB;
+        V* betab = reinterpret_cast<V*>(L.betab) + team * RS;
         V* ring = reinterpret_cast<V*>(L.ring) + team * RS * RS;
         if (tl < RS) ring[((Mp + tl) % RS) * RS + tl] = (tl == 0) ? vone<V>() : vzero<V>();
         V pik = (tl == 0) ? vone<V>() : vzero<V>();
