@@ -29,10 +29,10 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU (vect
 # sources hashed here: any change to them reports null until re-measured.
 TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_amd/csrc/charpoly_l88.hip")
 TRAFFIC = {
-    "sha256": "aead400b108d5cca35efcaf39a25082146c438237d2eb732f66e2a4a7cdf75c8",
+    "sha256": "3cdfbcaa7a59dcb7143e9e174c6304ca56f28216bbf382484e49b3f7f3f516d6",
     "kernel": "charpoly_kernel<8, 8, 4, 4, double2, 64>",
-    "fetch_bytes": 821658,      # 401.2 KiB FETCH_SIZE x 2.0
-    "write_bytes": 219213414,   # 214075.6 KiB WRITE_SIZE x 1.0
+    "fetch_bytes": 826481,      # 403.6 KiB FETCH_SIZE x 2.0
+    "write_bytes": 219213421,   # 214075.6 KiB WRITE_SIZE x 1.0
 }
 
 

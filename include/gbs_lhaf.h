@@ -268,7 +268,9 @@ typedef enum {
     GBS_LAYOUT_DEFAULT = -1, /* heuristic, or the autotuned choice when one exists */
     GBS_LAYOUT_4x4 = 0,      /* 16 lanes per subset, 4 subsets per wavefront, m <= 24 */
     GBS_LAYOUT_8x4 = 1,      /* 32 lanes per subset, 2 subsets per wavefront, m <= 40 */
-    GBS_LAYOUT_8x8 = 2       /* 64 lanes per subset, m <= 64                          */
+    GBS_LAYOUT_8x8 = 2,      /* 64 lanes per subset, m <= 64                          */
+    GBS_LAYOUT_8x4_ONE_TEAM = 3 /* 8x4 grid, one 64-lane La Budde team serving both subsets
+                                   in turn (half the LDS of two 32-lane teams), m <= 40 */
 } gbs_layout;
 
 /* Use `layout` for subsets of size s (m = 2s vertices) whenever the loop
@@ -281,7 +283,7 @@ gbs_status gbs_set_layout(int32_t n, int32_t s, int32_t layout);
 typedef struct {
     int32_t n;
     int32_t layout[33];           /* chosen grid per subset size s = 1..n    */
-    double ns_per_subset[33][3];  /* measured time per subset, 0 = not valid */
+    double ns_per_subset[33][4];  /* measured time per subset, 0 = not valid */
 } gbs_tune_report;
 
 /* Project autotuner: for every subset size s of an n-pair loop hafnian, times

@@ -42,10 +42,10 @@ class gbs_diag(ctypes.Structure):
 
 
 class gbs_tune_report(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("layout", ctypes.c_int32 * 33), ("ns_per_subset", (ctypes.c_double * 3) * 33)]
+    _fields_ = [("n", ctypes.c_int32), ("layout", ctypes.c_int32 * 33), ("ns_per_subset", (ctypes.c_double * 4) * 33)]
 
 
-LAYOUTS = {0: "4x4", 1: "8x4", 2: "8x8"}
+LAYOUTS = {0: "4x4", 1: "8x4", 2: "8x8", 3: "8x4/1"}
 
 
 class gbs_batch_info(ctypes.Structure):
@@ -363,7 +363,7 @@ def autotune(n):
     _check(lib().gbs_autotune(int(n), ctypes.byref(r)))
     out = {}
     for s in range(1, n + 1):
-        times = {LAYOUTS[k]: r.ns_per_subset[s][k] for k in range(3) if r.ns_per_subset[s][k] > 0}
+        times = {LAYOUTS[k]: r.ns_per_subset[s][k] for k in range(4) if r.ns_per_subset[s][k] > 0}
         out[s] = (LAYOUTS[r.layout[s]], times)
     return out
 

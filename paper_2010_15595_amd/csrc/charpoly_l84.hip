@@ -23,29 +23,29 @@ static hipError_t launch_charpoly_team(const LaunchPhase1& p, hipStream_t st) {
 }
 
 template <int P, int Q, int MR, int MC>
-static hipError_t launch_charpoly_t(const LaunchPhase1& p, hipStream_t st) {
+static hipError_t launch_charpoly_t(const LaunchPhase1& p, hipStream_t st, bool one_team) {
     constexpr int G = P * Q;
-    if (lb_variant(G, p.D) == 0) {
+    if (!one_team && lb_variant(G, p.D) == 0) {
         if constexpr (G < 64) return launch_charpoly_team<P, Q, MR, MC, G>(p, st);
         return hipErrorInvalidValue;
     }
     return launch_charpoly_team<P, Q, MR, MC, 64>(p, st);
 }
 
-hipError_t launch_charpoly_l84(const LaunchPhase1& p, hipStream_t st) {
+hipError_t launch_charpoly_l84(const LaunchPhase1& p, hipStream_t st, bool one_team) {
     const int m = 2 * p.s;
     const int mr = (m + 7) / 8, mc = (m + 3) / 4;
     switch (mc) {
-        case 1: return launch_charpoly_t<8, 4, 1, 1>(p, st);
-        case 2: return launch_charpoly_t<8, 4, 1, 2>(p, st);
-        case 3: return launch_charpoly_t<8, 4, 2, 3>(p, st);
-        case 4: return launch_charpoly_t<8, 4, 2, 4>(p, st);
-        case 5: return launch_charpoly_t<8, 4, 3, 5>(p, st);
-        case 6: return launch_charpoly_t<8, 4, 3, 6>(p, st);
-        case 7: return launch_charpoly_t<8, 4, 4, 7>(p, st);
-        case 8: return launch_charpoly_t<8, 4, 4, 8>(p, st);
-        case 9: return launch_charpoly_t<8, 4, 5, 9>(p, st);
-        case 10: return launch_charpoly_t<8, 4, 5, 10>(p, st);
+        case 1: return launch_charpoly_t<8, 4, 1, 1>(p, st, one_team);
+        case 2: return launch_charpoly_t<8, 4, 1, 2>(p, st, one_team);
+        case 3: return launch_charpoly_t<8, 4, 2, 3>(p, st, one_team);
+        case 4: return launch_charpoly_t<8, 4, 2, 4>(p, st, one_team);
+        case 5: return launch_charpoly_t<8, 4, 3, 5>(p, st, one_team);
+        case 6: return launch_charpoly_t<8, 4, 3, 6>(p, st, one_team);
+        case 7: return launch_charpoly_t<8, 4, 4, 7>(p, st, one_team);
+        case 8: return launch_charpoly_t<8, 4, 4, 8>(p, st, one_team);
+        case 9: return launch_charpoly_t<8, 4, 5, 9>(p, st, one_team);
+        case 10: return launch_charpoly_t<8, 4, 5, 10>(p, st, one_team);
     }
     (void)mr;
     return hipErrorInvalidValue;

@@ -785,7 +785,7 @@ __global__ void __launch_bounds__(64, charpoly_waves_per_simd(P, Q, MR, MC, true
         const BatchTile tl = tiles[t];
         const BatchItem it = items[tl.item];
         const int D = it.n + 1;
-        if (lb_team(G, D) != TEAM) continue;  // the plan groups tiles by team layout; never taken
+        if (TEAM < D + 1) continue;  // a team must hold D + 1 coefficients; the plan never sends such tiles
         const int4* lbm = lbmap + lb_table_offset(TEAM, D);
         for (uint64_t first = 0; first < tl.count; first += W)
             charpoly_wave<P, Q, MR, MC, V, TEAM>(it.A0, it.dvec, it.Np, tl.s, tl.rank0, tl.count, first, nullptr,

@@ -39,7 +39,9 @@ struct LaunchPhase2 {
 };
 
 // Lane grids of the per-subset kernel (rows x columns of lanes per subset).
-enum { kLayout44 = 0, kLayout84 = 1, kLayout88 = 2, kNumLayouts = 3 };
+// kLayout84T: the 8 x 4 grid with one 64-lane La Budde team serving both
+// subsets of the wavefront in turn (half the LDS of two 32-lane teams).
+enum { kLayout44 = 0, kLayout84 = 1, kLayout88 = 2, kLayout84T = 3, kNumLayouts = 4 };
 bool charpoly_layout_ok(int m, int layout);
 int charpoly_default_layout(int m);
 hipError_t launch_charpoly(const LaunchPhase1& p, int layout, hipStream_t st);

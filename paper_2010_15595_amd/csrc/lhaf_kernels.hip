@@ -389,7 +389,7 @@ __global__ void __launch_bounds__(64) selftest_kernel(const double* __restrict__
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_charpoly_l44(const LaunchPhase1& p, hipStream_t st);
-hipError_t launch_charpoly_l84(const LaunchPhase1& p, hipStream_t st);
+hipError_t launch_charpoly_l84(const LaunchPhase1& p, hipStream_t st, bool one_team);
 hipError_t launch_charpoly_l88(const LaunchPhase1& p, hipStream_t st);
 
 bool charpoly_layout_ok(int m, int layout) {
@@ -397,6 +397,7 @@ bool charpoly_layout_ok(int m, int layout) {
         case kLayout44: return m <= 24;
         case kLayout84: return m <= 40;
         case kLayout88: return m <= 64;
+        case kLayout84T: return m <= 40;
     }
     return false;
 }
@@ -418,11 +419,13 @@ int charpoly_instance(int layout, int s) {
     switch (layout) {
         case kLayout44: return 100 + (m + 3) / 4;
         case kLayout84: return 200 + (m + 3) / 4;
+        case kLayout84T: return 400 + (m + 3) / 4;
         default: return 300 + (m + 7) / 8;
     }
 }
 
 int charpoly_variant(int layout, int n) {
+    if (layout == kLayout84T) return 1;
     const int G = (layout == kLayout44) ? 16 : (layout == kLayout84) ? 32 : 64;
     return lb_variant(G, n + 1);
 }
@@ -482,6 +485,7 @@ hipError_t launch_charpoly_batch(int layout, int s_rep, int variant, int D_max, 
         case kLayout44:
             return launch_charpoly_batch_l44(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
         case kLayout84:
+        case kLayout84T:
             return launch_charpoly_batch_l84(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
         default:
             return launch_charpoly_batch_l88(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
@@ -673,7 +677,8 @@ hipError_t launch_charpoly(const LaunchPhase1& p, int layout, hipStream_t st) {
     if (!charpoly_layout_ok(m, layout)) return hipErrorInvalidValue;
     switch (layout) {
         case kLayout44: return launch_charpoly_l44(p, st);
-        case kLayout84: return launch_charpoly_l84(p, st);
+        case kLayout84: return launch_charpoly_l84(p, st, false);
+        case kLayout84T: return launch_charpoly_l84(p, st, true);
         default: return launch_charpoly_l88(p, st);
     }
 }

@@ -129,3 +129,20 @@ def test_batch_edge_items(gbs):
 def test_batch_rejects_bad_dims(gbs):
     with pytest.raises(gbs.GbsError):
         gbs.BatchPlan([10, 70])
+
+
+def test_batch_with_one_team_layout(gbs):
+    """Batch tiles on the 8x4 grid with one 64-lane La Budde team (forced for
+    every subset size it can hold) against single evaluations on the default
+    grids: the team guard of the batch kernel must let these tiles through."""
+    dims, mats = _items(24, seed=7, lo=18, hi=34)
+    gbs.set_layout(0, 0, 3)
+    try:
+        plan = gbs.BatchPlan(dims)
+        got, ab = _run(gbs, plan, mats)
+        plan.close()
+    finally:
+        gbs.set_layout(0, 0, -1)
+    for i, A in enumerate(mats):
+        single, d = gbs.lhaf(A, with_diag=True)
+        assert abs(got[i] - single) <= NORMWISE * d["abs_sum"], (i, dims[i])

@@ -257,9 +257,10 @@ def test_allones_accuracy_report(gbs):
         assert abs(val - T) <= NORMWISE * d["abs_sum"]
 
 
-@pytest.mark.parametrize("layout,N", [(0, 24), (1, 24), (2, 24), (1, 40), (2, 40)])
+@pytest.mark.parametrize("layout,N", [(0, 24), (1, 24), (2, 24), (3, 24), (1, 40), (2, 40), (3, 40)])
 def test_every_lane_grid_matches_oracle(gbs, layout, N):
-    """Each lane grid of the per-subset kernel (4x4, 8x4, 8x8), forced for all
+    """Each lane grid of the per-subset kernel (4x4, 8x4, 8x8, 8x4 with one
+    La Budde team), forced for all
     subset sizes, against the oracle: full sum at N = 24, sampled terms at 40."""
     st = workloads.config3(N, seed=5)
     A = oracle.expand(st["B"], st["gamma"], st["pattern"])
