@@ -101,7 +101,7 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
         }
         for (int s = 1; s <= n; ++s) {
             const uint64_t cnt = binom_host(n, s);
-            const int lay = layout_for(c, n, s);
+            const int lay = layout_for(c, n, s, true);
             for (uint64_t r0 = 0; r0 < cnt; r0 += (uint64_t)tile_subsets) {
                 HostTile h{};
                 h.t.rank0 = r0;

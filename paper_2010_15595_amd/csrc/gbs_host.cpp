@@ -46,7 +46,12 @@ uint64_t binom_host(int a, int b) {
     return r;
 }
 
-int layout_for(const DevCtx* c, int n, int s) {
+int layout_for(const DevCtx* c, int n, int s, bool batch) {
+    if (batch) {
+        if (c->layout_multi[n][s] >= 0) return c->layout_multi[n][s];
+        // measured slower inside batches than the two-team 8x4 grid
+        if (c->layout[n][s] == gbs::kLayout84T) return gbs::kLayout84;
+    }
     const int v = c->layout[n][s];
     return v >= 0 ? v : gbs::charpoly_default_layout(2 * s);
 }
@@ -875,7 +880,7 @@ gbs_status gbs_set_layout(int32_t n, int32_t s, int32_t layout) {
     if (st != GBS_OK) return st;
     for (int nn = (n ? n : 1); nn <= (n ? n : gbs::kMaxPairs); ++nn)
         for (int ss = (s ? s : 1); ss <= (s ? s : nn); ++ss)
-            if (layout < 0 || gbs::charpoly_layout_ok(2 * ss, layout)) c->layout[nn][ss] = layout;
+            if (layout < 0 || gbs::charpoly_layout_ok(2 * ss, layout)) c->layout[nn][ss] = c->layout_multi[nn][ss] = layout;
     return GBS_OK;
 }
 
@@ -889,15 +894,17 @@ bool cache_load(DevCtx* c, int n) {
     if (!path || !*path) return false;
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
-    char arch[64];
-    int nn, ss, lay;
+    char line[256], arch[64];
+    int nn, ss, lay, lay_multi;
     bool any = false;
-    while (std::fscanf(f, "%63s %d %d %d", arch, &nn, &ss, &lay) == 4) {
-        if (nn == n && std::strcmp(arch, c->name) == 0 && ss >= 1 && ss <= n && lay >= 0 &&
-            lay < gbs::kNumLayouts && gbs::charpoly_layout_ok(2 * ss, lay)) {
-            c->layout[n][ss] = lay;
-            any = true;
-        }
+    auto ok = [&](int l) { return l >= 0 && l < gbs::kNumLayouts && gbs::charpoly_layout_ok(2 * ss, l); };
+    // "<arch> <n> <s> <layout> [<batch layout>]"
+    while (std::fgets(line, sizeof line, f)) {
+        const int k = std::sscanf(line, "%63s %d %d %d %d", arch, &nn, &ss, &lay, &lay_multi);
+        if (k < 4 || nn != n || std::strcmp(arch, c->name) != 0 || ss < 1 || ss > n || !ok(lay)) continue;
+        c->layout[n][ss] = lay;
+        c->layout_multi[n][ss] = (k == 5 && ok(lay_multi)) ? lay_multi : -1;
+        any = true;
     }
     std::fclose(f);
     return any;
@@ -908,7 +915,8 @@ void cache_store(const DevCtx* c, int n) {
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    for (int s = 1; s <= n; ++s) std::fprintf(f, "%s %d %d %d\n", c->name, n, s, c->layout[n][s]);
+    for (int s = 1; s <= n; ++s)
+        std::fprintf(f, "%s %d %d %d %d\n", c->name, n, s, c->layout[n][s], c->layout_multi[n][s]);
     std::fclose(f);
 }
 
@@ -941,12 +949,18 @@ gbs_status autotune_impl(DevCtx* c, int n, gbs_tune_report* rep) {
         std::memset(rep, 0, sizeof *rep);
         rep->n = n;
     }
+    // GBS_AUTOTUNE_LAYOUTS: bit mask of the lane grids the tuner may choose (default: all)
+    unsigned mask = (1u << gbs::kNumLayouts) - 1u;
+    if (const char* e = std::getenv("GBS_AUTOTUNE_LAYOUTS")) {
+        const unsigned v = (unsigned)strtoul(e, nullptr, 0) & mask;
+        if (v) mask = v;
+    }
     for (int s = 1; s <= n; ++s) {
         const uint64_t len = std::min(sample_cap, binom_host(n, s));
-        double best = 1e300;
-        int best_lay = gbs::charpoly_default_layout(2 * s);
+        double best = 1e300, best_multi = 1e300;
+        int best_lay = gbs::charpoly_default_layout(2 * s), best_lay_multi = -1;
         for (int lay = 0; lay < gbs::kNumLayouts; ++lay) {
-            if (!gbs::charpoly_layout_ok(2 * s, lay)) continue;
+            if (!gbs::charpoly_layout_ok(2 * s, lay) || !((mask >> lay) & 1u)) continue;
             gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, nullptr, c->binom, D, c->E, 0, c->lbmap};
             HIP_TRY(gbs::launch_charpoly(p1, lay, c->stream));  // warm-up
             HIP_TRY(hipEventRecord(c->t0, c->stream));
@@ -962,8 +976,13 @@ gbs_status autotune_impl(DevCtx* c, int n, gbs_tune_report* rep) {
                 best = ns;
                 best_lay = lay;
             }
+            if (lay != gbs::kLayout84T && ns < best_multi) {
+                best_multi = ns;
+                best_lay_multi = lay;
+            }
         }
         c->layout[n][s] = best_lay;
+        c->layout_multi[n][s] = best_lay_multi;
         if (rep) rep->layout[s] = best_lay;
     }
     HIP_TRY(hipEventRecord(c->done, c->stream));

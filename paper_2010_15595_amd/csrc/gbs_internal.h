@@ -57,12 +57,17 @@ struct DevCtx {
     BatchRunner* runner = nullptr;  // eager batch runner of the sampling chain, created on first use
     void* smats = nullptr;          // packed loop-hafnian matrices of one sampling step
     size_t smats_cap = 0;           // bytes
-    // lane grid per (n, s); -1 = heuristic default
+    // lane grid per (n, s); -1 = heuristic default.  layout_multi is the
+    // choice for batch plans, where many launches share the device: the
+    // tuner's best among the grids with one La Budde team per subset group
     int layout[gbs::kMaxPairs + 1][gbs::kMaxPairs + 1];
+    int layout_multi[gbs::kMaxPairs + 1][gbs::kMaxPairs + 1];
     bool tuned[gbs::kMaxPairs + 1];
     char name[64] = {0};
     DevCtx() {
         for (auto& row : layout)
+            for (int& v : row) v = -1;
+        for (auto& row : layout_multi)
             for (int& v : row) v = -1;
         for (bool& t : tuned) t = false;
     }
@@ -71,7 +76,9 @@ struct DevCtx {
 extern std::mutex g_mutex;  // serialises every library call
 
 gbs_status current_ctx(DevCtx** out);
-int layout_for(const DevCtx* c, int n, int s);
+// Lane grid of subsets of size s of an n-pair loop hafnian; batch = true
+// gives the batch-plan choice.
+int layout_for(const DevCtx* c, int n, int s, bool batch = false);
 // Consults the autotune cache / runs the tuner once per n (uses the workspace,
 // so it is called before the caller's matrix is prepared).
 gbs_status maybe_tune(DevCtx* c, int n);
