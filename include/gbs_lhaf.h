@@ -308,6 +308,10 @@ typedef struct {
     int64_t reduce_launches;
     double charpoly_flops;     /* algorithmic flops of the profiled subsets (see gbs_yardstick_flops) */
     double subset_terms;       /* subsets processed by the profiled launches                        */
+    char dominant_kernel[96];  /* per-subset kernel instance with the largest summed duration    */
+    double dominant_ms;        /* its summed duration                                           */
+    double dominant_flops;     /* its algorithmic flops (yardstick of its subsets)             */
+    int64_t dominant_launches; /* its launches                                                  */
 } gbs_profile;
 
 /* on = 1 clears the counters and starts recording; on = 0 stops recording. */

@@ -63,7 +63,9 @@ class gbs_profile(ctypes.Structure):
     _fields_ = [("charpoly_ms", ctypes.c_double), ("series_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double),
                 ("charpoly_launches", ctypes.c_int64), ("series_launches", ctypes.c_int64),
                 ("reduce_launches", ctypes.c_int64), ("charpoly_flops", ctypes.c_double),
-                ("subset_terms", ctypes.c_double)]
+                ("subset_terms", ctypes.c_double), ("dominant_kernel", ctypes.c_char * 96),
+                ("dominant_ms", ctypes.c_double), ("dominant_flops", ctypes.c_double),
+                ("dominant_launches", ctypes.c_int64)]
 
 
 _L = None
@@ -344,7 +346,9 @@ def profile_enable(on=True):
 def profile_read():
     p = gbs_profile()
     _check(lib().gbs_profile_read(ctypes.byref(p)))
-    return {f: getattr(p, f) for f, _ in gbs_profile._fields_}
+    out = {f: getattr(p, f) for f, _ in gbs_profile._fields_}
+    out["dominant_kernel"] = p.dominant_kernel.decode()
+    return out
 
 
 def yardstick_flops(N):

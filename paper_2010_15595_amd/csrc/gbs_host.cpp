@@ -65,6 +65,7 @@ struct ProfRec {
     int kind;
     hipEvent_t a, b;
     double flops, subsets;
+    std::string kernel;  // instance name of a per-subset launch
 };
 bool g_prof = false;
 std::vector<ProfRec> g_prof_recs;
@@ -76,9 +77,10 @@ double subset_flops(int n, int s) {
 
 // Records an event pair around `launch` when profiling is on.
 template <class F>
-hipError_t timed_launch(int kind, double flops, double subsets, hipStream_t st, F&& launch) {
+hipError_t timed_launch(int kind, double flops, double subsets, hipStream_t st, F&& launch,
+                        const std::string& kernel = std::string()) {
     if (!g_prof) return launch();
-    ProfRec r{kind, nullptr, nullptr, flops, subsets};
+    ProfRec r{kind, nullptr, nullptr, flops, subsets, kernel};
     hipError_t e = hipEventCreate(&r.a);
     if (e != hipSuccess) return e;
     e = hipEventCreate(&r.b);
@@ -241,6 +243,18 @@ gbs_status expand_impl(const gbs_z* B, int32_t M, int64_t ldb, const gbs_z* gamm
 }
 
 // Subset-sum schedule on prepared workspace (ctx->A0, ctx->dvec).
+// Name of the per-subset kernel instance a launch of subsets of size s runs
+// (as the profiler prints it), for per-instance timing.
+std::string charpoly_instance_name(int lay, int s, int D, bool fp32) {
+    const int P = (lay == gbs::kLayout44) ? 4 : 8, Q = (lay == gbs::kLayout88) ? 8 : 4, m = 2 * s;
+    const int G = P * Q;
+    const int team = gbs::charpoly_variant(lay, D - 1) != 0 ? 64 : G;
+    char buf[96];
+    snprintf(buf, sizeof buf, "charpoly_kernel<%d, %d, %d, %d, %s, %d>", P, Q, (m + P - 1) / P, (m + Q - 1) / Q,
+             fp32 ? "float2" : "double2", team);
+    return buf;
+}
+
 // Subset sum on the LDS-resident kernels (double-double, or FP64 with either
 // characteristic-polynomial method): per size class and chunk, one workgroup
 // per subset writes its term, a block reduction folds them into dd partials,
@@ -274,10 +288,14 @@ gbs_status run_sum_lds(DevCtx* c, int Np, hipStream_t st, double2* out_dev, doub
         const double sign = ((n - s) & 1) ? -1.0 : 1.0;
         for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
             const uint64_t len = std::min(kChunk, cnt - st0);
-            HIP_TRY(timed_launch(kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st, [&] {
-                return gbs::launch_charpoly_lds(prec_dd, method, c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D,
-                                                sign, c->E, st);
-            }));
+            HIP_TRY(timed_launch(
+                kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
+                [&] {
+                    return gbs::launch_charpoly_lds(prec_dd, method, c->A0, c->dvec, Np, s, st0, len, nullptr,
+                                                    c->binom, D, sign, c->E, st);
+                },
+                prec_dd ? "charpoly_lds_kernel<ArDD, 0>"
+                        : (method == gbs::kCharpolyEigen ? "charpoly_lds_kernel<ArF64, 1>" : "charpoly_lds_kernel<ArF64, 0>")));
             HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, st, [&] {
                 return gbs::launch_lds_block_reduce(prec_dd, c->E, len, kLdsPer, c->partials + 5 * poff, nullptr, st);
             }));
@@ -332,8 +350,9 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
             const uint64_t len = std::min(kChunk, cnt - st0);
             gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, c->E, fp32 ? 1 : 0, c->lbmap};
             const int lay = layout_for(c, n, s);
-            HIP_TRY(timed_launch(kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
-                                 [&] { return gbs::launch_charpoly(p1, lay, st); }));
+            HIP_TRY(timed_launch(
+                kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
+                [&] { return gbs::launch_charpoly(p1, lay, st); }, charpoly_instance_name(lay, s, D, fp32)));
             gbs::LaunchPhase2 p2{c->E, fp32 ? 1 : 0, len, D, sign, kPerThread, c->partials + 5 * poff, nullptr};
             HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, st, [&] { return gbs::launch_series(n, p2, st); }));
             poff += (len + per_block - 1) / per_block;
@@ -837,6 +856,11 @@ gbs_status gbs_profile_read(gbs_profile* out) {
     if (!out) return fail(GBS_E_ARG, "null output");
     std::lock_guard<std::mutex> lock(g_mutex);
     gbs_profile p{};
+    struct Inst {
+        double ms = 0.0, flops = 0.0;
+        int64_t launches = 0;
+    };
+    std::map<std::string, Inst> inst;
     for (auto& r : g_prof_recs) {
         HIP_TRY(hipEventSynchronize(r.b));
         float ms = 0.f;
@@ -846,6 +870,10 @@ gbs_status gbs_profile_read(gbs_profile* out) {
             p.charpoly_launches += 1;
             p.charpoly_flops += r.flops;
             p.subset_terms += r.subsets;
+            Inst& q = inst[r.kernel];
+            q.ms += ms;
+            q.flops += r.flops;
+            q.launches += 1;
         } else if (r.kind == kProfSeries) {
             p.series_ms += ms;
             p.series_launches += 1;
@@ -857,6 +885,18 @@ gbs_status gbs_profile_read(gbs_profile* out) {
         hipEventDestroy(r.b);
     }
     g_prof_recs.clear();
+    // the instance with the largest summed duration
+    const Inst* best = nullptr;
+    for (const auto& kv : inst)
+        if (!best || kv.second.ms > best->ms) {
+            best = &kv.second;
+            snprintf(p.dominant_kernel, sizeof p.dominant_kernel, "%s", kv.first.c_str());
+        }
+    if (best) {
+        p.dominant_ms = best->ms;
+        p.dominant_flops = best->flops;
+        p.dominant_launches = best->launches;
+    }
     *out = p;
     return GBS_OK;
 }
