@@ -146,3 +146,28 @@ def test_batch_with_one_team_layout(gbs):
     for i, A in enumerate(mats):
         single, d = gbs.lhaf(A, with_diag=True)
         assert abs(got[i] - single) <= NORMWISE * d["abs_sum"], (i, dims[i])
+
+
+def test_full_size_chain_workload(gbs):
+    """The 4096-item chain-like workload the batch benchmark replays, in the
+    same plan configuration: sampled items (the largest among them) against
+    single evaluations, and the items with N <= 16 among them against the oracle."""
+    st = workloads.config4(count=4096)
+    mats = [gbs.expand(st["B"], st["gamma"], pat) for pat in st["patterns"]]
+    dims = [a.shape[0] for a in mats]
+    plan = gbs.BatchPlan(dims)
+    got, ab = _run(gbs, plan, mats)
+    plan.close()
+    order = np.argsort(dims)
+    pick = sorted(set([int(i) for i in order[-8:]] + [int(i) for i in order[:8]] +
+                      [int(i) for i in np.random.default_rng(1).choice(len(mats), 16, replace=False)]))
+    worst = 0.0
+    for i in pick:
+        single, d = gbs.lhaf(mats[i], with_diag=True)
+        assert abs(got[i] - single) <= NORMWISE * d["abs_sum"], (i, dims[i])
+        worst = max(worst, abs(got[i] - single) / d["abs_sum"])
+        if dims[i] <= 16:
+            ref = oracle.to_complex(oracle.lhaf_pt(mats[i], prec="ld"))
+            assert abs(got[i] - ref) <= max(1e-10 * abs(ref), NORMWISE * ab[i]), (i, dims[i])
+    print(f"[batch 4096] {len(pick)} sampled items, N {min(dims)}..{max(dims)}, worst |batch-single|/sum|t| "
+          f"{worst:.2e}", flush=True)
