@@ -62,7 +62,9 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
     const int64_t vbytes = fp32 ? (int64_t)sizeof(float2) : (int64_t)sizeof(double2);
     const int nitems = S.count;
 
-    // items
+    // items (flop yardstick per dimension computed once)
+    double flops_of[GBS_MAX_DIM + 1];
+    bool have_flops[GBS_MAX_DIM + 1] = {};
     S.in_off.resize(nitems);
     S.a0_off.resize(nitems);
     S.d_off.resize(nitems);
@@ -78,7 +80,11 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
         S.d_elems += Np;
         S.max_n = std::max(S.max_n, Np / 2);
         S.subset_terms += (int64_t)1 << (Np / 2);
-        S.flops += gbs_yardstick_flops(N);
+        if (!have_flops[N]) {
+            flops_of[N] = gbs_yardstick_flops(N);
+            have_flops[N] = true;
+        }
+        S.flops += flops_of[N];
     }
 
     // tiles: (item, s, rank range); series blocks and partial ranges per item
@@ -116,7 +122,12 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
             }
         }
     }
-    std::stable_sort(S.small.begin(), S.small.end(), [&](int a, int b) { return S.npair[a] > S.npair[b]; });
+    {  // largest n first, stable: a counting sort over n = 1..small_pairs
+        std::vector<int> by_n[gbs::kSmallPairs + 1];
+        for (int i : S.small) by_n[S.npair[i]].push_back(i);
+        S.small.clear();
+        for (int n = gbs::kSmallPairs; n >= 1; --n) S.small.insert(S.small.end(), by_n[n].begin(), by_n[n].end());
+    }
     // partials: per item contiguous, in (item, s, rank) order
     S.pbeg.assign(nitems + 1, 0);
     std::vector<int64_t> tile_pidx(ht.size());
