@@ -274,6 +274,27 @@ def bench_sampler(args, gbs):
         "host_setup_ms": info["setup_ms"],
         "mean_photons": float(s.sum(axis=1).mean()),
     }
+    if not args.no_cpu_baseline:
+        # the oracle chain (numpy conditioning, long-double loop hafnians) on the first samples of the
+        # same random numbers, for about args.cpu_seconds; its draws must equal the GPU's
+        from oracle import sampler as osampler
+
+        t0 = time.perf_counter()
+        done = 0
+        while done < n and (done < 8 or time.perf_counter() - t0 < args.cpu_seconds):
+            ref = osampler.sample_chain(st["Q"], st["alpha_vec"], cutoff, z[done], u[done])
+            if list(ref) != [int(x) for x in s[done]]:
+                log(f"WARNING: oracle sample {done} differs from the GPU's: {ref} vs {list(s[done])}")
+            done += 1
+        dt = time.perf_counter() - t0
+        import oracle
+
+        result["cpu_baseline"] = {"value": done / dt, "unit": "samples/s", "cores": oracle.max_threads(),
+                                  "kind": "oracle", "seconds": dt,
+                                  "sample": f"the first {done} samples of the same workload and random numbers "
+                                  "through the oracle's sampling chain (numpy conditioning; its C loop hafnians may "
+                                  "use the OpenMP threads counted in cores)"}
+        log(f"cpu baseline: {done} oracle samples in {dt:.1f} s")
     print(json.dumps(result), flush=True)
 
 
