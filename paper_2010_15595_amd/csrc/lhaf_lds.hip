@@ -592,12 +592,17 @@ template <class Ar, int METHOD>
 hipError_t launch_lds_t(const double2* A0, const double2* dvec, int Np, int s, uint64_t rank0, uint64_t count,
                         const uint64_t* masks, const uint64_t* binom, int D, double sign, void* terms, size_t lds,
                         size_t lds_max, hipStream_t st) {
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&charpoly_lds_kernel<Ar, METHOD>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+    // the dynamic-LDS limit is a per-device attribute of the kernel (callers hold the library lock)
+    static bool attr[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (!attr[dev]) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&charpoly_lds_kernel<Ar, METHOD>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
         if (e != hipSuccess) return e;
-        attr = true;
+        attr[dev] = true;
     }
     hipLaunchKernelGGL((charpoly_lds_kernel<Ar, METHOD>), dim3((unsigned)count), dim3(kLdsThreads), lds, st, A0, dvec,
                        Np, s, rank0, masks, binom, D, sign, static_cast<typename Ar::C*>(terms));
