@@ -27,12 +27,13 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU (vect
 # on a plain 256 MiB device copy (fetch x2.0, write x1.0); the command and raw
 # figures are in profiles/charpoly_n50_traffic.md.  Valid only for the kernel
 # sources hashed here: any change to them reports null until re-measured.
-TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_amd/csrc/charpoly_l88.hip")
+TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_amd/csrc/charpoly_l88.hip",
+                   "paper_2010_15595_amd/csrc/lhaf_kernels.h")
 TRAFFIC = {
-    "sha256": "3cdfbcaa7a59dcb7143e9e174c6304ca56f28216bbf382484e49b3f7f3f516d6",
-    "kernel": "charpoly_kernel<8, 8, 4, 4, double2, 64>",
-    "fetch_bytes": 826481,      # 403.6 KiB FETCH_SIZE x 2.0
-    "write_bytes": 219213421,   # 214075.6 KiB WRITE_SIZE x 1.0
+    "sha256": "89518d440fc58b5a58ad77665500d1095f1f9505fd463d9e1df42d8a6d3f89d8",
+    "kernel": "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>",
+    "fetch_bytes": 825549,      # 403.1 KiB FETCH_SIZE x 2.0
+    "write_bytes": 213955174,   # 208940.6 KiB WRITE_SIZE x 1.0
 }
 
 

@@ -5,21 +5,40 @@
 
 namespace gbs {
 
-template <int P, int Q, int MR, int MC, int TEAM>
-static hipError_t launch_charpoly_team(const LaunchPhase1& p, hipStream_t st) {
+template <int P, int Q, int MR, int MC, int TEAM, int O>
+static hipError_t launch_charpoly_inst(const LaunchPhase1& p, hipStream_t st) {
     constexpr int W = 64 / (P * Q);
     const unsigned grid = (unsigned)((p.count + W - 1) / W);
     const int4* lbm = p.lbmap + lb_table_offset(TEAM, p.D);
     if (p.fp32) {
         const size_t lds = charpoly_lds_bytes(W, TEAM, p.D, sizeof(float2));
-        hipLaunchKernelGGL((charpoly_kernel<P, Q, MR, MC, float2, TEAM>), dim3(grid), dim3(64), lds, st, p.A0, p.dvec,
+        hipLaunchKernelGGL((charpoly_kernel<P, Q, MR, MC, float2, TEAM, O>), dim3(grid), dim3(64), lds, st, p.A0, p.dvec,
                            p.Np, p.s, p.rank0, p.count, p.masks, p.binom, p.D, lbm, static_cast<float2*>(p.Eout));
     } else {
         const size_t lds = charpoly_lds_bytes(W, TEAM, p.D, sizeof(double2));
-        hipLaunchKernelGGL((charpoly_kernel<P, Q, MR, MC, double2, TEAM>), dim3(grid), dim3(64), lds, st, p.A0, p.dvec,
+        hipLaunchKernelGGL((charpoly_kernel<P, Q, MR, MC, double2, TEAM, O>), dim3(grid), dim3(64), lds, st, p.A0, p.dvec,
                            p.Np, p.s, p.rank0, p.count, p.masks, p.binom, p.D, lbm, static_cast<double2*>(p.Eout));
     }
     return hipGetLastError();
+}
+
+// Tile offset of C (charpoly_front_offset): even, below Q.
+template <int P, int Q, int MR, int MC, int TEAM>
+static hipError_t launch_charpoly_team(const LaunchPhase1& p, hipStream_t st) {
+    if constexpr (MC >= 3) {
+        switch (charpoly_front_offset(P, Q, MR, MC, 2 * p.s)) {
+            case 0: return launch_charpoly_inst<P, Q, MR, MC, TEAM, 0>(p, st);
+            case 2: return launch_charpoly_inst<P, Q, MR, MC, TEAM, 2>(p, st);
+            case 4:
+                if constexpr (Q == 8) return launch_charpoly_inst<P, Q, MR, MC, TEAM, 4>(p, st);
+                break;
+            case 6:
+                if constexpr (Q == 8) return launch_charpoly_inst<P, Q, MR, MC, TEAM, 6>(p, st);
+                break;
+        }
+        return hipErrorInvalidValue;
+    }
+    return launch_charpoly_inst<P, Q, MR, MC, TEAM, 0>(p, st);
 }
 
 template <int P, int Q, int MR, int MC>

@@ -249,9 +249,10 @@ std::string charpoly_instance_name(int lay, int s, int D, bool fp32) {
     const int P = (lay == gbs::kLayout44) ? 4 : 8, Q = (lay == gbs::kLayout88) ? 8 : 4, m = 2 * s;
     const int G = P * Q;
     const int team = gbs::charpoly_variant(lay, D - 1) != 0 ? 64 : G;
+    const int MR = (m + P - 1) / P, MC = (m + Q - 1) / Q;
     char buf[96];
-    snprintf(buf, sizeof buf, "charpoly_kernel<%d, %d, %d, %d, %s, %d>", P, Q, (m + P - 1) / P, (m + Q - 1) / Q,
-             fp32 ? "float2" : "double2", team);
+    snprintf(buf, sizeof buf, "charpoly_kernel<%d, %d, %d, %d, %s, %d, %d>", P, Q, MR, MC, fp32 ? "float2" : "double2",
+             team, gbs::charpoly_front_offset(P, Q, MR, MC, m));
     return buf;
 }
 

@@ -421,13 +421,18 @@ __host__ __device__ constexpr size_t charpoly_lds_bytes(int W, int T, int D, int
     return lds_layout(W, T, D, vbytes).total;
 }
 
-template <int P, int Q, int MR, int MC, int KJ>
+// Hessenberg reduction of the tile holding C at rows and columns O .. O+m-1
+// (indices below O are zero padding): reflector j (a tile index) zeroes
+// column j below row j + 1, for j = O .. O+m-3; phase KJ takes the columns of
+// local index KJ.
+template <int P, int Q, int MR, int MC, int KJ, int O>
 __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC], int m, int pr, int pc,
                                            double2* __restrict__ vb, double2* __restrict__ nb) {
     constexpr int IL = (Q * KJ) / P;  // local rows below IL lie above every column of this phase
-    for (int jj = 0; jj < Q; ++jj) {
+    constexpr int jj0 = (O > Q * KJ) ? O - Q * KJ : 0;
+    for (int jj = jj0; jj < Q; ++jj) {
         const int j = Q * KJ + jj;
-        if (j > m - 3) return;
+        if (j > O + m - 3) return;
         wave_sync();
         if (pc == jj) {
             double part = 0.0;
@@ -481,13 +486,17 @@ __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC
     }
 }
 
-template <int P, int Q, int MR, int MC, int KJ>
+template <int P, int Q, int MR, int MC, int KJ, int O>
 __device__ __forceinline__ void hess_all(double2 (&a)[MR][MC], double2 (&y)[MC], int m, int pr, int pc,
                                          double2* __restrict__ vb, double2* __restrict__ nb) {
     if constexpr (KJ < MC) {
-        if (Q * KJ > m - 3) return;
-        hess_phase<P, Q, MR, MC, KJ>(a, y, m, pr, pc, vb, nb);
-        hess_all<P, Q, MR, MC, KJ + 1>(a, y, m, pr, pc, vb, nb);
+        if constexpr (Q * KJ + Q <= O) {  // the phase lies wholly in the padding
+            hess_all<P, Q, MR, MC, KJ + 1, O>(a, y, m, pr, pc, vb, nb);
+            return;
+        }
+        if (Q * KJ > O + m - 3) return;
+        hess_phase<P, Q, MR, MC, KJ, O>(a, y, m, pr, pc, vb, nb);
+        hess_all<P, Q, MR, MC, KJ + 1, O>(a, y, m, pr, pc, vb, nb);
     }
 }
 
@@ -544,7 +553,10 @@ __device__ __forceinline__ void labudde_step(int rho, int m, int D, int tl, int4
     wave_sync();
 }
 
-template <int P, int Q, int MR, int MC, int I, class V>
+// Rows of the tile are read bottom-up into rowbuf_own at their tile column
+// indices; C sits at tile offset O, so rowbuf (already advanced by O) holds the
+// row in C's own column indices and rho is C's row index.
+template <int P, int Q, int MR, int MC, int I, class V, int O>
 __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, int D, int tl, int4 mp, int gmax,
                                              typename CxT<V>::S m1, typename CxT<V>::S m2, int pr, int pc,
                                              bool row_owner_group, double2* __restrict__ rowbuf_own,
@@ -552,8 +564,8 @@ __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, 
                                              V* __restrict__ ring, V& pik, V& sub) {
     if constexpr (I >= 0) {
         for (int p = P - 1; p >= 0; --p) {
-            const int rho = p + P * I;
-            if (rho >= m) continue;
+            const int rho = p + P * I - O;
+            if (rho >= m || rho < 0) continue;
             if (row_owner_group && pr == p) {
 #pragma unroll
                 for (int k = 0; k < MC; ++k) rowbuf_own[pc + Q * k] = a[I][k];
@@ -564,8 +576,8 @@ __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, 
             labudde_step<V>(rho, m, D, tl, mp, gmax, m1, m2, hrr, sub, pik, rowbuf, betab, ring);
             sub = sub_next;
         }
-        labudde_rows<P, Q, MR, MC, I - 1, V>(a, m, D, tl, mp, gmax, m1, m2, pr, pc, row_owner_group, rowbuf_own,
-                                             rowbuf, betab, ring, pik, sub);
+        labudde_rows<P, Q, MR, MC, I - 1, V, O>(a, m, D, tl, mp, gmax, m1, m2, pr, pc, row_owner_group, rowbuf_own,
+                                                rowbuf, betab, ring, pik, sub);
     }
 }
 
@@ -585,7 +597,7 @@ __host__ __device__ constexpr int charpoly_waves_per_simd(int P, int Q, int MR, 
 // the FP64 path, float2 for the FP32 path; the Hessenberg reduction is FP64).
 // La Budde teams have TEAM lanes (P Q, or 64 when a subset needs more than
 // P Q coefficient lanes), fixed per launch; lbm is the lane map of (TEAM, D).
-template <int P, int Q, int MR, int MC, class V, int TEAM>
+template <int P, int Q, int MR, int MC, class V, int TEAM, int O = 0>
 __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, const double2* __restrict__ dvec, int Np,
                                               int s, uint64_t rank0, uint64_t count, uint64_t first,
                                               const uint64_t* __restrict__ masks, const uint64_t* __restrict__ binom,
@@ -645,21 +657,26 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     }
     wave_sync();
 
-    // gather C = X_S A0_S, border row y = d_S and border column z = X_S d_S
+    // gather C = X_S A0_S, border row y = d_S and border column z = X_S d_S.
+    // C occupies tile rows and columns O .. O+m-1 of the P MR x Q MC tile
+    // (O + m <= min(P MR, Q MC)); zero padding in front is passed by the
+    // reflectors of the first phase and dropped by later phases with their
+    // local index.
+    constexpr int o = O;
     double2 a[MR][MC];
     double2 y[MC];
     double2 zr[MR], zc[MC];
 #pragma unroll
     for (int i = 0; i < MR; ++i) {
-        const int r = pr + P * i;
-        const bool rok = r < m;
+        const int r = pr + P * i - o;
+        const bool rok = r >= 0 && r < m;
         const int xr = (r < s) ? r + s : r - s;
         const int vr = rok ? idx[xr] : 0;
         zr[i] = rok ? dvec[vr] : cz();
 #pragma unroll
         for (int k = 0; k < MC; ++k) {
-            const int c = pc + Q * k;
-            const bool ok = rok && c < m;
+            const int c = pc + Q * k - o;
+            const bool ok = rok && c >= 0 && c < m;
             const int off = ok ? vr * Np + idx[c] : 0;
             const double2 v = A0[off];
             a[i][k] = ok ? v : cz();
@@ -667,8 +684,8 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     }
 #pragma unroll
     for (int k = 0; k < MC; ++k) {
-        const int c = pc + Q * k;
-        const bool ok = c < m;
+        const int c = pc + Q * k - o;
+        const bool ok = c >= 0 && c < m;
         const int xc = (c < s) ? c + s : c - s;
         const double2 dy = dvec[ok ? idx[c] : 0];
         const double2 dz = dvec[ok ? idx[xc] : 0];
@@ -689,9 +706,9 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         householder(norm2, x0, scale, vhead, alpha);
         double2 vr[MR], vc[MC];
 #pragma unroll
-        for (int i = 0; i < MR; ++i) vr[i] = (pr + P * i == 0) ? vhead : cscale(zr[i], scale);
+        for (int i = 0; i < MR; ++i) vr[i] = (pr + P * i == o) ? vhead : cscale(zr[i], scale);
 #pragma unroll
-        for (int k = 0; k < MC; ++k) vc[k] = (pc + Q * k == 0) ? vhead : cscale(zc[k], scale);
+        for (int k = 0; k < MC; ++k) vc[k] = (pc + Q * k == o) ? vhead : cscale(zc[k], scale);
 #pragma unroll
         for (int k = 0; k < MC; ++k) {
             double2 w = cz();
@@ -706,7 +723,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     if (lane % G == 0) nb[1] = alpha;
 
     // Householder reduction of the C block
-    hess_all<P, Q, MR, MC, 0>(a, y, m, pr, pc, vb, nb);
+    hess_all<P, Q, MR, MC, 0, O>(a, y, m, pr, pc, vb, nb);
     // vbuf and idx are dead from here on; the La Budde ring reuses their space
     wave_sync();
 
@@ -724,15 +741,15 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         const int gt = pass * NT + team;          // group served by my team
         const bool own = (g / NT) == pass;        // my group's rows are read this pass
         double2* rowbuf_own = L.rowbuf + (g % NT) * RB;
-        double2* rowbuf = L.rowbuf + team * RB;
+        const double2* rowbuf = L.rowbuf + team * RB + o;  // C's column 0
         V* betab = reinterpret_cast<V*>(L.betab) + team * RS;
         V* ring = reinterpret_cast<V*>(L.ring) + team * RS * RS;
         if (tl < RS) ring[((Mp + tl) % RS) * RS + tl] = (tl == 0) ? vone<V>() : vzero<V>();
         V pik = (tl == 0) ? vone<V>() : vzero<V>();
         V sub = vzero<V>();
         wave_sync();
-        labudde_rows<P, Q, MR, MC, MR - 1, V>(a, m, D, tl, mp, gmax, m1, m2, pr, pc, own, rowbuf_own, rowbuf, betab,
-                                              ring, pik, sub);
+        labudde_rows<P, Q, MR, MC, MR - 1, V, O>(a, m, D, tl, mp, gmax, m1, m2, pr, pc, own, rowbuf_own, rowbuf,
+                                                 betab, ring, pik, sub);
         // border row: H'[0][k] = y''_{k-1}, H'[0][0] = 0, H'[1][0] = alpha
         if (own && pr == 0) {
 #pragma unroll
@@ -752,15 +769,15 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
 }
 
 
-template <int P, int Q, int MR, int MC, class V, int TEAM>
+template <int P, int Q, int MR, int MC, class V, int TEAM, int O>
 __global__ void __launch_bounds__(64, charpoly_waves_per_simd(P, Q, MR, MC, false))
     charpoly_kernel(const double2* __restrict__ A0, const double2* __restrict__ dvec, int Np, int s, uint64_t rank0,
                     uint64_t count, const uint64_t* __restrict__ masks, const uint64_t* __restrict__ binom, int D,
                     const int4* __restrict__ lbm, V* __restrict__ Eout) {
     extern __shared__ double2 lds[];
     constexpr int W = 64 / (P * Q);
-    charpoly_wave<P, Q, MR, MC, V, TEAM>(A0, dvec, Np, s, rank0, count, (uint64_t)blockIdx.x * W, masks, binom, D, lbm,
-                                         Eout, lds);
+    charpoly_wave<P, Q, MR, MC, V, TEAM, O>(A0, dvec, Np, s, rank0, count, (uint64_t)blockIdx.x * W, masks, binom, D,
+                                            lbm, Eout, lds);
 }
 
 // Persistent form for batches: every wavefront takes tiles from `tiles`

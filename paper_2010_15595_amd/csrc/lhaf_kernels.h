@@ -9,6 +9,15 @@ namespace gbs {
 constexpr int kMaxPairs = 32;       // n = N / 2 <= 32 (N <= 64)
 constexpr int kBinomStride = 33;    // binomial table C(a, b), 0 <= a, b <= 32
 
+// Offset of C (m x m, m even) in the P MR x Q MC register tile of a
+// single-evaluation launch (MC = ceil(m / Q)): tiles of three or more local
+// columns put their spare rows and columns in front (offset 2, 4 or 6 on
+// 8-column grids, 2 on 4-column grids), which shortens the first Householder
+// phase; smaller tiles, and every batch launch, keep them behind (offset 0).
+__host__ __device__ constexpr int charpoly_front_offset(int P, int Q, int MR, int MC, int m) {
+    return (MC >= 3) ? ((P * MR < Q * MC ? P * MR : Q * MC) - m) : 0;
+}
+
 // Phase 1: one wavefront per pair subset of size s; writes, per subset, the
 // D + 1 leading coefficients of det(xI - C) then of det(xI - C').
 struct LaunchPhase1 {
