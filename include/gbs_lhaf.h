@@ -289,8 +289,12 @@ typedef struct {
 /* Project autotuner: for every subset size s of an n-pair loop hafnian, times
  * each valid lane grid on a sample of that size class (HIP events, synthetic
  * matrix; the work is data-independent) and keeps the fastest for the current
- * device; batch plans use the fastest grid other than GBS_LAYOUT_8x4_ONE_TEAM
- * (measured slower when many launches share the device).  With GBS_AUTOTUNE_CACHE=<path> in the environment the choices are
+ * device (report->ns_per_subset holds those single-evaluation timings).
+ * Batch plans use the fastest grid other than GBS_LAYOUT_8x4_ONE_TEAM
+ * (measured slower when many launches share the device), timed in the form
+ * batch tiles run: the subset block at tile offset 0.  GBS_FP32_COMP
+ * evaluations run GBS_LAYOUT_8x4 where GBS_LAYOUT_8x4_ONE_TEAM was chosen.
+ * With GBS_AUTOTUNE_CACHE=<path> in the environment the choices are
  * appended to / read from that file; GBS_AUTOTUNE_LAYOUTS=<bit mask of
  * gbs_layout values> restricts the candidates.  report may be NULL. */
 gbs_status gbs_autotune(int32_t n, gbs_tune_report *report);

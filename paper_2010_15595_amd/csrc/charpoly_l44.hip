@@ -26,7 +26,7 @@ static hipError_t launch_charpoly_inst(const LaunchPhase1& p, hipStream_t st) {
 template <int P, int Q, int MR, int MC, int TEAM>
 static hipError_t launch_charpoly_team(const LaunchPhase1& p, hipStream_t st) {
     if constexpr (MC >= 3) {
-        switch (charpoly_front_offset(P, Q, MR, MC, 2 * p.s)) {
+        switch (p.no_offset ? 0 : charpoly_front_offset(P, Q, MR, MC, 2 * p.s)) {
             case 0: return launch_charpoly_inst<P, Q, MR, MC, TEAM, 0>(p, st);
             case 2: return launch_charpoly_inst<P, Q, MR, MC, TEAM, 2>(p, st);
             case 4:

@@ -46,14 +46,24 @@ uint64_t binom_host(int a, int b) {
     return r;
 }
 
-int layout_for(const DevCtx* c, int n, int s, bool batch) {
+int layout_for(const DevCtx* c, int n, int s, bool batch, bool fp32) {
     if (batch) {
         if (c->layout_multi[n][s] >= 0) return c->layout_multi[n][s];
         // measured slower inside batches than the two-team 8x4 grid
         if (c->layout[n][s] == gbs::kLayout84T) return gbs::kLayout84;
     }
     const int v = c->layout[n][s];
+    // the tuner times the FP64 kernels; the FP32 La Budde instances of the
+    // one-team 8x4 grid need 250-300 VGPRs (one or two waves per SIMD), and
+    // the two-team grid ran N = 50 18% faster in FP32
+    if (fp32 && v == gbs::kLayout84T) return gbs::kLayout84;
     return v >= 0 ? v : gbs::charpoly_default_layout(2 * s);
+}
+
+// Tile offset of C in a single-evaluation launch of size-s subsets on `lay`.
+int layout_front_offset(int lay, int s) {
+    const int P = (lay == gbs::kLayout44) ? 4 : 8, Q = (lay == gbs::kLayout88) ? 8 : 4, m = 2 * s;
+    return gbs::charpoly_front_offset(P, Q, (m + P - 1) / P, (m + Q - 1) / Q, m);
 }
 
 std::mutex g_mutex;
@@ -249,10 +259,9 @@ std::string charpoly_instance_name(int lay, int s, int D, bool fp32) {
     const int P = (lay == gbs::kLayout44) ? 4 : 8, Q = (lay == gbs::kLayout88) ? 8 : 4, m = 2 * s;
     const int G = P * Q;
     const int team = gbs::charpoly_variant(lay, D - 1) != 0 ? 64 : G;
-    const int MR = (m + P - 1) / P, MC = (m + Q - 1) / Q;
     char buf[96];
-    snprintf(buf, sizeof buf, "charpoly_kernel<%d, %d, %d, %d, %s, %d, %d>", P, Q, MR, MC, fp32 ? "float2" : "double2",
-             team, gbs::charpoly_front_offset(P, Q, MR, MC, m));
+    snprintf(buf, sizeof buf, "charpoly_kernel<%d, %d, %d, %d, %s, %d, %d>", P, Q, (m + P - 1) / P, (m + Q - 1) / Q,
+             fp32 ? "float2" : "double2", team, layout_front_offset(lay, s));
     return buf;
 }
 
@@ -350,7 +359,7 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
         for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
             const uint64_t len = std::min(kChunk, cnt - st0);
             gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, c->E, fp32 ? 1 : 0, c->lbmap};
-            const int lay = layout_for(c, n, s);
+            const int lay = layout_for(c, n, s, false, fp32);
             HIP_TRY(timed_launch(
                 kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
                 [&] { return gbs::launch_charpoly(p1, lay, st); }, charpoly_instance_name(lay, s, D, fp32)));
@@ -804,7 +813,7 @@ gbs_status gbs_lhaf_terms(const gbs_z* A, int32_t N, int64_t lda, const uint64_t
             } else {
                 gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, c->E, fp32 ? 1 : 0,
                                      c->lbmap};
-                HIP_TRY(gbs::launch_charpoly(p1, layout_for(c, n, s), c->stream));
+                HIP_TRY(gbs::launch_charpoly(p1, layout_for(c, n, s, false, fp32), c->stream));
                 gbs::LaunchPhase2 p2{c->E, fp32 ? 1 : 0, len, D, sign, kPerThread, c->partials, c->terms};
                 HIP_TRY(gbs::launch_series(n, p2, c->stream));
             }
@@ -1003,21 +1012,34 @@ gbs_status autotune_impl(DevCtx* c, int n, gbs_tune_report* rep) {
         for (int lay = 0; lay < gbs::kNumLayouts; ++lay) {
             if (!gbs::charpoly_layout_ok(2 * s, lay) || !((mask >> lay) & 1u)) continue;
             gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, nullptr, c->binom, D, c->E, 0, c->lbmap};
-            HIP_TRY(gbs::launch_charpoly(p1, lay, c->stream));  // warm-up
-            HIP_TRY(hipEventRecord(c->t0, c->stream));
-            const int reps = 3;
-            for (int r = 0; r < reps; ++r) HIP_TRY(gbs::launch_charpoly(p1, lay, c->stream));
-            HIP_TRY(hipEventRecord(c->t1, c->stream));
-            HIP_TRY(hipEventSynchronize(c->t1));
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, c->t0, c->t1));
-            const double ns = 1e6 * ms / (reps * (double)len);
+            auto time_ns = [&](double* ns) -> hipError_t {
+                hipError_t e = gbs::launch_charpoly(p1, lay, c->stream);  // warm-up
+                if (e != hipSuccess) return e;
+                if ((e = hipEventRecord(c->t0, c->stream)) != hipSuccess) return e;
+                const int reps = 3;
+                for (int r = 0; r < reps; ++r)
+                    if ((e = gbs::launch_charpoly(p1, lay, c->stream)) != hipSuccess) return e;
+                if ((e = hipEventRecord(c->t1, c->stream)) != hipSuccess) return e;
+                if ((e = hipEventSynchronize(c->t1)) != hipSuccess) return e;
+                float ms = 0.f;
+                if ((e = hipEventElapsedTime(&ms, c->t0, c->t1)) != hipSuccess) return e;
+                *ns = 1e6 * ms / (reps * (double)len);
+                return hipSuccess;
+            };
+            double ns = 0.0;
+            HIP_TRY(time_ns(&ns));
             if (rep) rep->ns_per_subset[s][lay] = ns;
             if (ns < best) {
                 best = ns;
                 best_lay = lay;
             }
-            if (lay != gbs::kLayout84T && ns < best_multi) {
+            if (lay == gbs::kLayout84T) continue;
+            // batch tiles keep C at offset 0: time that form for the batch choice
+            if (layout_front_offset(lay, s) != 0) {
+                p1.no_offset = 1;
+                HIP_TRY(time_ns(&ns));
+            }
+            if (ns < best_multi) {
                 best_multi = ns;
                 best_lay_multi = lay;
             }

@@ -78,7 +78,7 @@ extern std::mutex g_mutex;  // serialises every library call
 gbs_status current_ctx(DevCtx** out);
 // Lane grid of subsets of size s of an n-pair loop hafnian; batch = true
 // gives the batch-plan choice.
-int layout_for(const DevCtx* c, int n, int s, bool batch = false);
+int layout_for(const DevCtx* c, int n, int s, bool batch = false, bool fp32 = false);
 // Consults the autotune cache / runs the tuner once per n (uses the workspace,
 // so it is called before the caller's matrix is prepared).
 gbs_status maybe_tune(DevCtx* c, int n);

@@ -33,6 +33,7 @@ struct LaunchPhase1 {
     void* Eout;            // count * 2 * (D + 1) complex (double2, or float2 when fp32)
     int fp32;              // La Budde in complex FP32
     const int4* lbmap;     // La Budde lane maps of every (team width, D) (lb_fill_table)
+    int no_offset = 0;     // 1: C at tile offset 0 (the layout of batch tiles), else charpoly_front_offset
 };
 
 // Phase 2: one lane per subset; signed terms, compensated block partials.
