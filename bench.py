@@ -30,10 +30,10 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU (vect
 TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_amd/csrc/charpoly_l88.hip",
                    "paper_2010_15595_amd/csrc/lhaf_kernels.h")
 TRAFFIC = {
-    "sha256": "89518d440fc58b5a58ad77665500d1095f1f9505fd463d9e1df42d8a6d3f89d8",
+    "sha256": "451e5f4655d2c15f62746ab970eb76a2afe3607ee4ac45f80ee77a01a1e7df10",
     "kernel": "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>",
-    "fetch_bytes": 825549,      # 403.1 KiB FETCH_SIZE x 2.0
-    "write_bytes": 213955174,   # 208940.6 KiB WRITE_SIZE x 1.0
+    "fetch_bytes": 826332,      # 403.5 KiB FETCH_SIZE x 2.0
+    "write_bytes": 213955200,   # 208940.6 KiB WRITE_SIZE x 1.0
 }
 
 

@@ -223,6 +223,21 @@ def test_rank_one_n50(gbs):
     assert report("rank one N=50", val, oracle.telephone(50) * np.prod(v), d["abs_sum"])
 
 
+def test_tuned_launch_configuration_n50(gbs):
+    """N = 50 in the lane grids the autotuner picks (the configuration bench.py
+    times: one-team 8x4 and 8x8 grids with C at tile offsets 2, 4 and 6 among
+    them): the block-diagonal and rank-one closed forms over the full sum, and
+    sampled subset terms of the benchmark workload against the oracle."""
+    rep = gbs.autotune(25)
+    try:
+        print("[tuned n=25] " + ", ".join(f"s={s}:{lay}" for s, (lay, _) in rep.items()), flush=True)
+        test_n50_block_diagonal_product(gbs)
+        test_rank_one_n50(gbs)
+        test_sampled_subset_terms_full_size(gbs, 50)
+    finally:
+        gbs.set_layout(25, 0, -1)
+
+
 def test_bitwise_determinism_and_device_path(gbs):
     import torch
 
@@ -314,6 +329,23 @@ def test_fp32_path_small(gbs, N):
     err = abs(val - ref)
     print(f"[fp32 N={N}] rel err {err / abs(ref):.2e}, normwise {err / d['abs_sum']:.2e}, kappa {d['kappa']:.2e}",
           flush=True)
+    assert err <= FP32_NORMWISE * d["abs_sum"]
+
+
+@pytest.mark.parametrize("layout", [0, 1, 2, 3])
+def test_fp32_every_lane_grid(gbs, layout):
+    """The FP32 La Budde instances of each lane grid (each tile offset of C
+    among them), forced for all subset sizes at N = 24, against the oracle;
+    the one-team 8x4 choice runs the two-team grid in FP32."""
+    A = workloads.random_normal_symmetric(24, seed=640 + layout, scale=0.5)
+    gbs.set_layout(0, 0, layout)
+    try:
+        val, d = gbs.lhaf(A, prec=gbs.GBS_FP32_COMP, with_diag=True)
+    finally:
+        gbs.set_layout(0, 0, -1)
+    ref = oracle.to_complex(oracle.lhaf_pt(A, prec="ld"))
+    err = abs(val - ref)
+    print(f"[fp32 layout {layout} N=24] normwise {err / d['abs_sum']:.2e}", flush=True)
     assert err <= FP32_NORMWISE * d["abs_sum"]
 
 
