@@ -65,9 +65,48 @@ def workload(N):
     return st
 
 
-def cpu_baseline(A, N, seconds):
-    """The oracle (double, all host threads) on a uniform random sample of the
-    workload's pair subsets; scaled to lhaf/s by 2^n subsets per lhaf."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _terms_rate(A, n, seconds, threads, rng):
+    """Subset terms per second of the fp64 oracle over uniform random pair
+    subsets, on `threads` OpenMP threads, for about `seconds`."""
+    import numpy as np
+
+    import oracle
+
+    probe = rng.integers(0, 1 << n, size=max(64, 8 * threads), dtype=np.uint64)
+    t0 = time.perf_counter()
+    oracle.terms(A, probe, prec="d", nthreads=threads)
+    dt = time.perf_counter() - t0
+    rate = len(probe) / dt
+    # the probe underestimates the rate (thread start-up); resize once from a real sample
+    cap = 1.5e7
+    count = len(probe)
+    for _ in range(2):
+        count = int(max(len(probe), min(rate * seconds, cap)))
+        sample = rng.integers(0, 1 << n, size=count, dtype=np.uint64)
+        t0 = time.perf_counter()
+        oracle.terms(A, sample, prec="d", nthreads=threads)
+        dt = time.perf_counter() - t0
+        rate = count / dt
+        if dt >= 0.5 * seconds or count >= cap:
+            break
+    return rate, count, dt
+
+
+def cpu_baseline(A, N, seconds, one_thread_seconds):
+    """The oracle (double) on a uniform random sample of the workload's pair
+    subsets, on all host threads and on one thread; scaled to lhaf/s by 2^n
+    subsets per lhaf."""
     import numpy as np
 
     import oracle
@@ -75,32 +114,81 @@ def cpu_baseline(A, N, seconds):
     n = N // 2
     rng = np.random.default_rng(1234)
     threads = oracle.max_threads()
-    probe = rng.integers(0, 1 << n, size=max(64, 8 * threads), dtype=np.uint64)
-    t0 = time.perf_counter()
-    oracle.terms(A, probe, prec="d")
-    dt = time.perf_counter() - t0
-    rate = len(probe) / dt
-    # the probe underestimates the rate (thread start-up); resize once from a real sample
-    cap = 1.5e7
-    for _ in range(2):
-        count = int(max(len(probe), min(rate * seconds, cap)))
-        sample = rng.integers(0, 1 << n, size=count, dtype=np.uint64)
-        t0 = time.perf_counter()
-        oracle.terms(A, sample, prec="d")
-        dt = time.perf_counter() - t0
-        rate = count / dt
-        if dt >= 0.5 * seconds or count >= cap:
-            break
-    return {
+    rate, count, dt = _terms_rate(A, n, seconds, threads, rng)
+    res = {
         "value": rate / float(1 << n),
         "unit": "lhaf/s",
         "cores": threads,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
         "subset_terms_per_s": rate,
         "seconds": dt,
         "sample": f"{count} pair subsets drawn uniformly from the 2^{n} of the N={N} workload, "
                   f"fp64 oracle (Householder Hessenberg + La Budde + mat-vec loop terms), "
                   f"{threads} OpenMP threads; lhaf/s = subset-terms/s / 2^{n}",
+    }
+    if one_thread_seconds > 0:
+        r1, c1, d1 = _terms_rate(A, n, one_thread_seconds, 1, rng)
+        res["one_thread"] = {"value": r1 / float(1 << n), "unit": "lhaf/s", "cores": 1,
+                             "subset_terms_per_s": r1, "seconds": d1, "sample": f"{c1} pair subsets, 1 thread"}
+    return res
+
+
+def batch_cpu_baseline(mats, seconds, one_thread_seconds):
+    """The oracle (double, full power-trace sums) on items drawn uniformly at
+    random from the batch, on all host threads and on one thread: items/s over
+    the sample (its mean cost estimates the batch's)."""
+    import numpy as np
+
+    import oracle
+
+    rng = np.random.default_rng(4321)
+    threads = oracle.max_threads()
+
+    def leg(sec, nthr):
+        done, t0 = 0, time.perf_counter()
+        dims = []
+        while done < 4 or time.perf_counter() - t0 < sec:
+            A = mats[int(rng.integers(0, len(mats)))]
+            oracle.lhaf_pt(A, prec="d", nthreads=nthr)
+            dims.append(A.shape[0])
+            done += 1
+        dt = time.perf_counter() - t0
+        return done / dt, done, dt, dims
+
+    rate, done, dt, dims = leg(seconds, threads)
+    res = {"value": rate, "unit": "lhaf/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+           "seconds": dt,
+           "sample": f"{done} items drawn uniformly from the {len(mats)} of the batch (mean N {np.mean(dims):.1f}), "
+                     f"full fp64 oracle power-trace sums, {threads} OpenMP threads"}
+    if one_thread_seconds > 0:
+        r1, d1, t1, dm1 = leg(one_thread_seconds, 1)
+        res["one_thread"] = {"value": r1, "unit": "lhaf/s", "cores": 1, "seconds": t1,
+                             "sample": f"{d1} items (mean N {np.mean(dm1):.1f}), 1 thread"}
+    return res
+
+
+def roofline_from_profile(prof, steps, note):
+    """Roofline entry of the dominant per-subset kernel instance: its yardstick
+    flops per launch over its average launch duration (HIP event pairs on the
+    launch streams)."""
+    achieved = prof["dominant_flops"] / (prof["dominant_ms"] / 1000.0) / 1e12 if prof["dominant_ms"] > 0 else None
+    achieved_all = prof["charpoly_flops"] / (prof["charpoly_ms"] / 1000.0) / 1e12 if prof["charpoly_ms"] > 0 else None
+    return {
+        "bound": "alu",
+        "kernel": prof["dominant_kernel"],
+        "kernel_note": note,
+        "achieved": achieved,
+        "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None,
+        "flops_per_launch": prof["dominant_flops"] / max(1, prof["dominant_launches"]),
+        "avg_launch_ms": prof["dominant_ms"] / max(1, prof["dominant_launches"]),
+        "launches_per_step": prof["dominant_launches"] / steps,
+        "all_per_subset_kernels": {"achieved": achieved_all,
+                                   "frac": (achieved_all / FP64_PEAK_TFLOPS) if achieved_all else None,
+                                   "launches_per_step": prof["charpoly_launches"] / steps,
+                                   "kernel_ms_per_step": prof["charpoly_ms"] / steps},
     }
 
 
@@ -175,6 +263,23 @@ def bench_batch(args, gbs):
                  "max_normwise_diff_vs_batch": float(np.max(np.abs(pv - res) / scale))}
         log(f"plain form: {len(mats)} single lhaf_device calls in {pms:.1f} ms = {plain['lhaf_per_s']:.1f} lhaf/s; "
             f"batch speedup {plain['ms'] / (gpu_ms / args.steps):.2f}x; max |diff|/sum|t| {plain['max_normwise_diff_vs_batch']:.2e}")
+    # roofline pass: the same schedule issued eagerly (graph replays cannot be
+    # bracketed by events per launch), every persistent launch timed on its stream
+    gbs.profile_enable(True)
+    for _ in range(args.roofline_steps):
+        plan.run(packed, out, ab, stream)
+    torch.cuda.synchronize()
+    prof = gbs.profile_read()
+    gbs.profile_enable(False)
+    if not np.array_equal(out.cpu().numpy(), res):
+        log("WARNING: eager (profiled) run differs from the graph replays")
+    roof = roofline_from_profile(prof, args.roofline_steps,
+                                 "persistent per-subset kernel of one (lane grid, tile) class over the batch's tiles; "
+                                 f"average launch from {args.roofline_steps} eager profiled run(s) of the captured "
+                                 "schedule right after the timed graph replays")
+    roof["traffic"] = None
+    log(f"roofline: {roof['kernel']} {roof['achieved']:.2f} TFLOP/s ({100 * roof['frac']:.1f}% of FP64 peak); "
+        f"all per-subset launches {roof['all_per_subset_kernels']['achieved']:.2f} TFLOP/s")
     result = {
         "metric": "loop hafnians/s and subset-terms/s, batched uneven N",
         "value": items_per_s,
@@ -202,8 +307,13 @@ def bench_batch(args, gbs):
         "pct_fp64_peak": 100.0 * flops_per_s / (FP64_PEAK_TFLOPS * 1e12),
         "plan_seconds": plan_s,
         "plain_form": plain,
+        "roofline": roof,
     }
     plan.close()
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on items of the batch for ~{args.cpu_seconds:.0f} s ...")
+        result["cpu_baseline"] = batch_cpu_baseline(mats, args.cpu_seconds, args.cpu_one_thread_seconds)
+        log(f"cpu baseline: {result['cpu_baseline']['value']:.2f} lhaf/s on {result['cpu_baseline']['cores']} threads")
     print(json.dumps(result), flush=True)
 
 
@@ -389,6 +499,77 @@ def fig2_accuracy(args, gbs):
           flush=True)
 
 
+def fig3_sweep(args, gbs):
+    """Fig. 3 of the paper: loop-hafnian time on random complex symmetric
+    matrices (Re, Im ~ U[0, 1), symmetrised) for even N, FP64 (and double-double
+    up to --fig3-dd-max) on the GPU beside the paper's long-double times on 96
+    vCPUs, with the dominant per-subset instance's roofline at each N."""
+    import numpy as np
+    import torch
+
+    from paper_2010_15595_amd import workloads
+
+    paper = {}
+    with open(os.path.join(ROOT, "tests", "golden", "fig3_times.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                paper[int(k)] = float(v)
+    torch.cuda.set_device(0)
+    gbs.init(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = torch.zeros(1, dtype=torch.complex128, device=dev)
+    ab = torch.zeros(1, dtype=torch.float64, device=dev)
+    rows = {}
+    for N in args.fig3_sizes:
+        A = workloads.random_uniform_symmetric(N, seed=N)
+        A_dev = torch.from_numpy(A).to(dev)
+        n = N // 2
+        if not args.no_autotune:
+            gbs.autotune(n)
+        gbs.lhaf_device(A_dev, out, ab, stream)
+        torch.cuda.synchronize()
+        # at least ~1 s of GPU time per size, whole loop hafnians
+        t0 = time.perf_counter()
+        gbs.lhaf_device(A_dev, out, ab, stream)
+        torch.cuda.synchronize()
+        est = time.perf_counter() - t0
+        steps = max(1, min(200, int(1.0 / max(est, 1e-6))))
+        gbs.profile_enable(True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(steps):
+            gbs.lhaf_device(A_dev, out, ab, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        prof = gbs.profile_read()
+        gbs.profile_enable(False)
+        sec = ev0.elapsed_time(ev1) / 1000.0 / steps
+        flops = gbs.yardstick_flops(N)
+        roof = roofline_from_profile(prof, steps, "gather + Householder Hessenberg + La Budde, one size class")
+        row = {"fp64_seconds": sec, "fp64_lhaf_per_s": 1.0 / sec, "subset_terms_per_s": float(1 << n) / sec,
+               "pct_fp64_peak": 100.0 * flops / sec / (FP64_PEAK_TFLOPS * 1e12),
+               "dominant_kernel": roof["kernel"], "dominant_frac": roof["frac"],
+               "paper_seconds": paper.get(N), "speedup_vs_paper": paper[N] / sec if N in paper else None,
+               "steps": steps}
+        if N <= args.fig3_dd_max:
+            gbs.lhaf(A, prec=gbs.GBS_DD)
+            t0 = time.perf_counter()
+            _, d = gbs.lhaf(A, prec=gbs.GBS_DD, with_diag=True)
+            row["dd_seconds"] = d["kernel_ms"] / 1000.0
+            row["dd_speedup_vs_paper"] = paper[N] / row["dd_seconds"] if N in paper else None
+        if not args.no_autotune:
+            gbs.set_layout(n, 0, -1)
+        rows[N] = row
+        log(f"N={N}: {row}")
+    print(json.dumps({"metric": "loop-hafnian seconds vs N on Fig. 3 inputs (Sec. IV)", "unit": "s",
+                      "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "random complex symmetric N x N, Re, Im ~ U[0,1), (R + R^T)/2, seed N",
+                                 "paper": "long double, 96 vCPUs (Azure D96a v4, 2.345 GHz)"},
+                      "sizes": rows}), flush=True)
+
+
 def methods_comparison(args, gbs):
     """Sec. IV compares La Budde with diagonalisation: the same subset sum on
     the LDS-resident reference kernels with either method (FP64), beside the
@@ -423,6 +604,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-one-thread-seconds", type=float, default=8.0,
+                    help="length of the one-thread leg of the oracle baseline (0: skip)")
+    ap.add_argument("--roofline-steps", type=int, default=2,
+                    help="batch: eager profiled runs of the schedule for the roofline entry")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32comp", "dd"], default="fp64",
                     help="fp32comp: La Budde, series and per-lane sums in complex FP32 (Hessenberg FP64); "
@@ -433,7 +618,8 @@ def main():
                     help="print the hash of the kernel sources the traffic figures are tied to")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["n50", "batch", "sampler", "tvd", "fig2", "methods"], default="n50",
+    ap.add_argument("--workload", choices=["n50", "batch", "sampler", "tvd", "fig2", "fig3", "methods"],
+                    default="n50",
                     help="batch: 4096 loop hafnians of uneven N in [10, 36] from one 100-mode state, "
                          "one captured graph of persistent launches per step; sampler: samples/s of the "
                          "conditional sampling chain in the Fig. 1 setting; tvd: the Fig. 1 experiment")
@@ -444,6 +630,8 @@ def main():
     ap.add_argument("--method-sizes", type=int, nargs="+", default=[16, 24, 32, 36, 40])
     ap.add_argument("--fig2-sizes", type=int, nargs="+", default=[30, 34, 38, 42, 46, 48, 50])
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--fig3-sizes", type=int, nargs="+", default=list(range(30, 57, 2)))
+    ap.add_argument("--fig3-dd-max", type=int, default=44, help="fig3: largest N also timed in double-double")
     ap.add_argument("--no-plain", action="store_true", help="batch: skip timing the items one at a time")
     args = ap.parse_args()
     if args.print_source_hash:
@@ -488,6 +676,8 @@ def main():
         return fig2_accuracy(args, gbs)
     if args.workload == "methods":
         return methods_comparison(args, gbs)
+    if args.workload == "fig3":
+        return fig3_sweep(args, gbs)
 
     N = args.N
     st = workload(N)
@@ -606,7 +796,7 @@ def main():
     }
     if rank == 0 and not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a ~{args.cpu_seconds:.0f} s sample ...")
-        result["cpu_baseline"] = cpu_baseline(A, N, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(A, N, args.cpu_seconds, args.cpu_one_thread_seconds)
         log(f"cpu baseline: {result['cpu_baseline']['subset_terms_per_s']:.1f} subset-terms/s on "
             f"{result['cpu_baseline']['cores']} threads")
     print(json.dumps(result), flush=True)

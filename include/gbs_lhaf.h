@@ -23,7 +23,8 @@
  *   - lhaf(0 x 0) = 1.  An odd dimension is padded with one vertex that has
  *     loop weight 1 and no edges (the value is unchanged).  Pairs of the
  *     subset sum are (i, i + n), n = ceil(N / 2).
- *   - Largest supported dimension after expansion: GBS_MAX_DIM.
+ *   - Largest supported dimension after expansion: GBS_MAX_DIM for single
+ *     evaluations, GBS_MAX_BATCH_DIM for batch plans and the sampling chain.
  */
 #ifndef GBS_LHAF_H
 #define GBS_LHAF_H
@@ -35,6 +36,9 @@ extern "C" {
 #endif
 
 #define GBS_MAX_DIM 64
+/* Batch plans and the sampling chain run only the register-tile kernels, whose
+ * largest tile holds a 56 x 56 subset matrix without register spills. */
+#define GBS_MAX_BATCH_DIM 56
 
 typedef struct { double re, im; } gbs_z;
 
@@ -56,13 +60,16 @@ typedef enum {
     GBS_FP32_COMP = 1, /* Hessenberg reduction and all cross-lane / final sums in
                           binary64; La Budde, power-trace series and the per-lane
                           compensated (TwoSum) sums in complex binary32 */
-    GBS_DD = 2         /* every step of every subset term and every sum in
+    GBS_DD = 2,        /* every step of every subset term and every sum in
                           double-double (~106-bit significand; the paper's CPU
                           code uses x87 long double, 64 bits): single
                           evaluations with N <= 56 only (GBS_E_TOO_LARGE above,
                           GBS_E_UNSUPPORTED for batch plans and the sampler).
                           The result is hi + lo: out receives hi, and
                           gbs_diag.lhaf_lo the low part */
+    GBS_PRECISION_MAX_ENUM = 0x7FFFFFFF /* not a precision: makes every non-negative
+                          int32 value representable, so an unknown value is
+                          rejected (GBS_E_ARG) rather than undefined */
 } gbs_precision;
 
 /* Optional diagnostics of one loop-hafnian evaluation. */
@@ -129,9 +136,10 @@ gbs_status gbs_haf(const gbs_z *A, int32_t N, int64_t lda, gbs_precision prec, g
 /* Characteristic-polynomial method of the reference kernels. */
 typedef enum {
     GBS_CHARPOLY_LABUDDE = 0, /* La Budde over the Hessenberg form (the paper's method, Sec. IV) */
-    GBS_CHARPOLY_EIGEN = 1    /* eigenvalues of the Hessenberg form by the single-shift complex QR
+    GBS_CHARPOLY_EIGEN = 1,   /* eigenvalues of the Hessenberg form by the single-shift complex QR
                                  algorithm, multiplied out: the diagonalisation the paper compares
                                  La Budde with (Sec. IV) */
+    GBS_CHARPOLY_MAX_ENUM = 0x7FFFFFFF /* not a method (see GBS_PRECISION_MAX_ENUM) */
 } gbs_charpoly;
 
 /* lhaf of an N x N symmetric matrix A (leading dim lda, diagonal = loop weights)
@@ -202,7 +210,7 @@ typedef struct {
 
 #define GBS_PLAN_AUTOTUNE 1
 
-/* Plans a batch of `count` loop hafnians of dimensions dims[i] <= GBS_MAX_DIM
+/* Plans a batch of `count` loop hafnians of dimensions dims[i] <= GBS_MAX_BATCH_DIM
  * (the conditional-sampling chain of the paper's Sec. III produces such
  * batches: many loop hafnians of uneven size).  The input of a run is the
  * packed concatenation of the matrices: item i is an N_i x N_i row-major
@@ -213,7 +221,10 @@ typedef struct {
  * fixed-order compensated reduction per item; the whole schedule is captured
  * once into a HIP graph.  flags = GBS_PLAN_AUTOTUNE times candidate tile sizes
  * and the lane grid of every n in the batch on the device and keeps the
- * fastest.  Owns its device workspace until gbs_batch_plan_destroy. */
+ * fastest.  Owns its device workspace (including its own copies of the
+ * library's binomial and lane-map tables, so it stays valid across
+ * gbs_finalize / gbs_init) until gbs_batch_plan_destroy.  GBS_E_TOO_LARGE
+ * when an item exceeds GBS_MAX_BATCH_DIM. */
 gbs_status gbs_batch_plan_create(const int32_t *dims, int32_t count, gbs_precision prec, int32_t flags,
                                  gbs_plan **plan);
 gbs_status gbs_batch_plan_info(const gbs_plan *plan, gbs_batch_info *info);
@@ -253,8 +264,8 @@ typedef struct {
  * samples_out (nsamples x M) receives the patterns; probs_out (nullable,
  * nsamples x M x (cutoff + 1)) the normalised conditional probabilities each
  * draw used.  Every loop hafnian runs on the GPU; GBS_E_TOO_LARGE when a
- * sample's photons so far plus cutoff exceed GBS_MAX_DIM (never when
- * M * cutoff <= GBS_MAX_DIM), GBS_E_NONFINITE when a step's probabilities are
+ * sample's photons so far plus cutoff exceed GBS_MAX_BATCH_DIM (never when
+ * M * cutoff <= GBS_MAX_BATCH_DIM), GBS_E_NONFINITE when a step's probabilities are
  * not finite or all zero.  Host pointers; synchronous.  info may be NULL. */
 gbs_status gbs_sample_pure(const gbs_z *Q, const gbs_z *alpha, int32_t M, int32_t cutoff,
                            const double *normals, const double *uniforms, int32_t nsamples,
@@ -268,7 +279,8 @@ typedef enum {
     GBS_LAYOUT_DEFAULT = -1, /* heuristic, or the autotuned choice when one exists */
     GBS_LAYOUT_4x4 = 0,      /* 16 lanes per subset, 4 subsets per wavefront, m <= 24 */
     GBS_LAYOUT_8x4 = 1,      /* 32 lanes per subset, 2 subsets per wavefront, m <= 40 */
-    GBS_LAYOUT_8x8 = 2,      /* 64 lanes per subset, m <= 64                          */
+    GBS_LAYOUT_8x8 = 2,      /* 64 lanes per subset, m <= 56 (larger subsets of a
+                                single evaluation run on an LDS-resident FP64 kernel) */
     GBS_LAYOUT_8x4_ONE_TEAM = 3 /* 8x4 grid, one 64-lane La Budde team serving both subsets
                                    in turn (half the LDS of two 32-lane teams), m <= 40 */
 } gbs_layout;

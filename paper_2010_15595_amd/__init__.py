@@ -14,6 +14,8 @@ from ._lib import (  # noqa: F401
     GBS_FP32_COMP,
     GBS_FP64,
     GbsError,
+    MAX_BATCH_DIM,
+    MAX_DIM,
     autotune,
     expand,
     finalize,

@@ -11,13 +11,17 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgbs_lhaf.so")
+# GBS_LIB_PATH loads another build of the same library instead (e.g. the
+# host-sanitized build that tests/sanitize/run_host_asan.sh makes).
+LIB_PATH = os.environ.get("GBS_LIB_PATH") or os.path.join(HERE, "libgbs_lhaf.so")
 
 GBS_FP64 = 0
 GBS_FP32_COMP = 1
 GBS_DD = 2
 GBS_CHARPOLY_LABUDDE = 0
 GBS_CHARPOLY_EIGEN = 1
+MAX_DIM = 64  # GBS_MAX_DIM
+MAX_BATCH_DIM = 56  # GBS_MAX_BATCH_DIM
 
 STATUS = {
     0: "GBS_OK", -1: "GBS_E_ARG", -2: "GBS_E_NOT_SYMMETRIC", -3: "GBS_E_NONFINITE", -4: "GBS_E_TOO_LARGE",

@@ -121,8 +121,6 @@ hipError_t launch_charpoly_batch_l84(int s_rep, int variant, int D_max, int fp32
         case 6: return launch_charpoly_batch_t<8, 4, 3, 6>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
         case 7: return launch_charpoly_batch_t<8, 4, 4, 7>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
         case 8: return launch_charpoly_batch_t<8, 4, 4, 8>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
-        case 9: return launch_charpoly_batch_t<8, 4, 5, 9>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
-        case 10: return launch_charpoly_batch_t<8, 4, 5, 10>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
     }
     return hipErrorInvalidValue;
 }

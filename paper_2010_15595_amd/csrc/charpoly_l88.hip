@@ -61,7 +61,6 @@ hipError_t launch_charpoly_l88(const LaunchPhase1& p, hipStream_t st) {
         case 5: return launch_charpoly_t<8, 8, 5, 5>(p, st);
         case 6: return launch_charpoly_t<8, 8, 6, 6>(p, st);
         case 7: return launch_charpoly_t<8, 8, 7, 7>(p, st);
-        case 8: return launch_charpoly_t<8, 8, 8, 8>(p, st);
     }
     return hipErrorInvalidValue;
 }
@@ -116,7 +115,6 @@ hipError_t launch_charpoly_batch_l88(int s_rep, int variant, int D_max, int fp32
         case 5: return launch_charpoly_batch_t<8, 8, 5, 5>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
         case 6: return launch_charpoly_batch_t<8, 8, 6, 6>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
         case 7: return launch_charpoly_batch_t<8, 8, 7, 7>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
-        case 8: return launch_charpoly_batch_t<8, 8, 8, 8>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
     }
     return hipErrorInvalidValue;
 }

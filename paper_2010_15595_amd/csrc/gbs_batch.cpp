@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -48,6 +49,7 @@ struct gbs_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t t0 = nullptr, t1 = nullptr;
+    std::vector<hipEvent_t> eager_events;  // events of profiled eager runs, reused run to run
 };
 
 namespace gbs_host {
@@ -181,8 +183,20 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
                ht[dorder[e]].inst == ht[dorder[q]].inst)
             ++e;
         const HostTile& h = ht[dorder[q]];
-        S.cp.push_back(
-            CharpolyLaunch{h.round, h.layout, h.t.s, h.inst, h.variant, (int)q, (int)(e - q), (int)S.cp.size()});
+        CharpolyLaunch L{h.round, h.layout, h.t.s, h.inst, h.variant, (int)q, (int)(e - q), (int)S.cp.size()};
+        for (size_t k = q; k < e; ++k) {
+            L.flops += ht[dorder[k]].cost;
+            L.subsets += (double)ht[dorder[k]].t.count;
+        }
+        {
+            const int P = (h.layout == gbs::kLayout44) ? 4 : 8, Q = (h.layout == gbs::kLayout88) ? 8 : 4;
+            const int m = 2 * h.t.s, team = h.variant ? 64 : P * Q;
+            char buf[96];
+            snprintf(buf, sizeof buf, "charpoly_batch_kernel<%d, %d, %d, %d, %s, %d>", P, Q, (m + P - 1) / P,
+                     (m + Q - 1) / Q, fp32 ? "float2" : "double2", team);
+            L.kernel = buf;
+        }
+        S.cp.push_back(L);
         q = e;
     }
     // series blocks grouped by (round, n)
@@ -201,7 +215,8 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
 }
 
 gbs_status batch_enqueue(DevCtx* c, const BatchSchedule& S, const BatchDev& d, hipStream_t cs, hipStream_t* br,
-                         const std::function<hipError_t(hipEvent_t*)>& new_event) {
+                         const std::function<hipError_t(hipEvent_t*)>& new_event, bool prof) {
+    (void)c;
     const int nitems = S.count;
     HIP_TRY(gbs::launch_fill_u32(d.counters, (int)std::max<size_t>(1, S.cp.size()), cs));
     HIP_TRY(gbs::launch_batch_prep(d.mats, d.in_off, d.dims, d.items, nitems, cs));
@@ -212,7 +227,7 @@ gbs_status batch_enqueue(DevCtx* c, const BatchSchedule& S, const BatchDev& d, h
     if (!S.small.empty()) {
         hipStream_t bs = br[kBatchBranches - 1];
         HIP_TRY(hipStreamWaitEvent(bs, ev_prep, 0));
-        HIP_TRY(gbs::launch_small_items(d.small, (int)S.small.size(), d.items, c->binom, c->lbmap, d.out, d.abs,
+        HIP_TRY(gbs::launch_small_items(d.small, (int)S.small.size(), d.items, d.binom, d.lbmap, d.out, d.abs,
                                         kPersistentWaves, bs));
         HIP_TRY(new_event(&ev_small));
         HIP_TRY(hipEventRecord(ev_small, bs));
@@ -229,9 +244,15 @@ gbs_status batch_enqueue(DevCtx* c, const BatchSchedule& S, const BatchDev& d, h
             HIP_TRY(hipStreamWaitEvent(bs, ev_prep, 0));
             if (r >= 2) HIP_TRY(hipStreamWaitEvent(bs, ev_series[r - 2], 0));
             const int grid = std::min(L.ntiles, kPersistentWaves);
-            HIP_TRY(gbs::launch_charpoly_batch(L.layout, L.s_rep, L.variant, S.max_n + 1, S.fp32 ? 1 : 0,
-                                               d.tiles + L.tile_begin, L.ntiles, d.items, c->binom, c->lbmap,
-                                               d.counters + L.counter, E, grid, bs));
+            auto launch = [&]() {
+                return gbs::launch_charpoly_batch(L.layout, L.s_rep, L.variant, S.max_n + 1, S.fp32 ? 1 : 0,
+                                                  d.tiles + L.tile_begin, L.ntiles, d.items, d.binom, d.lbmap,
+                                                  d.counters + L.counter, E, grid, bs);
+            };
+            if (prof && profiling_on())
+                HIP_TRY(prof_charpoly_launch(L.flops, L.subsets, bs, launch, L.kernel));
+            else
+                HIP_TRY(launch());
             hipEvent_t ej;
             HIP_TRY(new_event(&ej));
             HIP_TRY(hipEventRecord(ej, bs));
@@ -258,7 +279,7 @@ namespace {
 template <class T>
 gbs_status upload(T** dst, const std::vector<T>& src, size_t* bytes) {
     const size_t nb = std::max<size_t>(1, src.size()) * sizeof(T);
-    hipError_t e = hipMalloc((void**)dst, nb);
+    hipError_t e = dev_malloc((void**)dst, nb);
     if (e != hipSuccess) return fail(GBS_E_NOMEM, "hipMalloc(%zu) failed: %s", nb, hipGetErrorString(e));
     *bytes += nb;
     if (!src.empty()) HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -267,7 +288,7 @@ gbs_status upload(T** dst, const std::vector<T>& src, size_t* bytes) {
 
 gbs_status dmalloc(void** dst, size_t nb, size_t* bytes) {
     nb = std::max<size_t>(nb, 16);
-    hipError_t e = hipMalloc(dst, nb);
+    hipError_t e = dev_malloc(dst, nb);
     if (e != hipSuccess) return fail(GBS_E_NOMEM, "hipMalloc(%zu) failed: %s", nb, hipGetErrorString(e));
     *bytes += nb;
     return GBS_OK;
@@ -278,14 +299,16 @@ void plan_free(gbs_plan* p) {
     if (p->exec) hipGraphExecDestroy(p->exec);
     if (p->graph) hipGraphDestroy(p->graph);
     for (hipEvent_t e : p->events) hipEventDestroy(e);
+    for (hipEvent_t e : p->eager_events) hipEventDestroy(e);
     if (p->t0) hipEventDestroy(p->t0);
     if (p->t1) hipEventDestroy(p->t1);
     for (hipStream_t s : p->br)
         if (s) hipStreamDestroy(s);
     if (p->cs) hipStreamDestroy(p->cs);
     const BatchDev& d = p->d;
-    void* bufs[] = {p->staging, d.a0,       d.dv,       d.items,   d.in_off,  d.dims, d.tiles, d.sblocks,
-                    d.pbeg,     d.partials, d.counters, d.ebuf[0], d.ebuf[1], d.out,  d.abs,   d.small};
+    void* bufs[] = {p->staging, d.a0,       d.dv,       d.items,   d.in_off,  d.dims, d.tiles,
+                    d.sblocks,  d.pbeg,     d.partials, d.counters, d.ebuf[0], d.ebuf[1], d.out,
+                    d.abs,      d.small,    const_cast<uint64_t*>(d.binom), const_cast<int4*>(d.lbmap)};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete p;
@@ -320,6 +343,18 @@ gbs_status plan_build_into(DevCtx* c, const std::vector<int>& dims, bool fp32, i
     if ((st = upload(&d.sblocks, S.sblocks, &B)) != GBS_OK) return st;
     if ((st = upload(&d.pbeg, S.pbeg, &B)) != GBS_OK) return st;
     if ((st = upload(&d.small, S.small, &B)) != GBS_OK) return st;
+    {  // the plan's own copies of the context's tables: a plan outlives gbs_finalize
+        void* tb = nullptr;
+        const size_t nb = sizeof(uint64_t) * gbs::kBinomStride * gbs::kBinomStride;
+        if ((st = dmalloc(&tb, nb, &B)) != GBS_OK) return st;
+        d.binom = static_cast<uint64_t*>(tb);
+        HIP_TRY(hipMemcpy(tb, c->binom, nb, hipMemcpyDeviceToDevice));
+        const size_t nl = sizeof(int4) * gbs::kLbTableEntries;
+        tb = nullptr;
+        if ((st = dmalloc(&tb, nl, &B)) != GBS_OK) return st;
+        d.lbmap = static_cast<int4*>(tb);
+        HIP_TRY(hipMemcpy(tb, c->lbmap, nl, hipMemcpyDeviceToDevice));
+    }
     if ((st = dmalloc((void**)&d.partials, sizeof(double) * 5 * (size_t)std::max<int64_t>(1, S.pbeg[nitems]), &B)) !=
         GBS_OK)
         return st;
@@ -341,7 +376,7 @@ gbs_status plan_build_into(DevCtx* c, const std::vector<int>& dims, bool fp32, i
         return r;
     };
     HIP_TRY(hipStreamBeginCapture(p->cs, hipStreamCaptureModeThreadLocal));
-    if ((st = batch_enqueue(c, S, d, p->cs, p->br, new_event)) != GBS_OK) return st;
+    if ((st = batch_enqueue(c, S, d, p->cs, p->br, new_event, false)) != GBS_OK) return st;
     HIP_TRY(hipStreamEndCapture(p->cs, &p->graph));
     HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
     return GBS_OK;
@@ -490,6 +525,8 @@ gbs_status runner_run(BatchRunner* r, const BatchSchedule& S, const double2* mat
     d.ebuf[1] = r->ebuf[1];
     d.out = (double2*)r->out;
     d.abs = (double*)r->abs;
+    d.binom = r->c->binom;  // the runner lives and dies with its context
+    d.lbmap = r->c->lbmap;
     if (before_sum) {
         const gbs_status e = before_sum(d.in_off, d.dims);
         if (e != GBS_OK) return e;
@@ -505,7 +542,7 @@ gbs_status runner_run(BatchRunner* r, const BatchSchedule& S, const double2* mat
         *e = r->events[r->ev_next++];
         return hipSuccess;
     };
-    return batch_enqueue(r->c, S, d, st, r->br, new_event);
+    return batch_enqueue(r->c, S, d, st, r->br, new_event, true);
 }
 
 }  // namespace gbs_host
@@ -514,11 +551,29 @@ namespace {
 
 int kernel_nodes_of(const gbs_plan* p) { return 3 + (int)p->S.cp.size() + (int)p->S.se.size(); }
 
-gbs_status plan_run(gbs_plan* p, const gbs_z* mats_dev, gbs_z* out_dev, double* abs_dev, hipStream_t s) {
+gbs_status plan_run(gbs_plan* p, const gbs_z* mats_dev, gbs_z* out_dev, double* abs_dev, hipStream_t s,
+                    bool prof = false) {
     if (p->S.in_elems > 0)
         HIP_TRY(hipMemcpyAsync(p->staging, mats_dev, sizeof(double2) * (size_t)p->S.in_elems, hipMemcpyDeviceToDevice,
                                s));
-    HIP_TRY(hipGraphLaunch(p->exec, s));
+    if (prof && profiling_on()) {
+        // the captured schedule issued eagerly, every per-subset launch timed on its own stream
+        size_t next = 0;
+        auto new_event = [p, &next](hipEvent_t* e) -> hipError_t {
+            if (next == p->eager_events.size()) {
+                hipEvent_t ev;
+                const hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                if (err != hipSuccess) return err;
+                p->eager_events.push_back(ev);
+            }
+            *e = p->eager_events[next++];
+            return hipSuccess;
+        };
+        const gbs_status st = batch_enqueue(nullptr, p->S, p->d, s, p->br, new_event, true);
+        if (st != GBS_OK) return st;
+    } else {
+        HIP_TRY(hipGraphLaunch(p->exec, s));
+    }
     if (out_dev) HIP_TRY(hipMemcpyAsync(out_dev, p->d.out, sizeof(double2) * p->S.count, hipMemcpyDeviceToDevice, s));
     if (abs_dev) HIP_TRY(hipMemcpyAsync(abs_dev, p->d.abs, sizeof(double) * p->S.count, hipMemcpyDeviceToDevice, s));
     return GBS_OK;
@@ -536,8 +591,9 @@ gbs_status gbs_batch_plan_create(const int32_t* dims, int32_t count, gbs_precisi
     std::vector<int> dv(count);
     for (int i = 0; i < count; ++i) {
         if (dims[i] < 0) return fail(GBS_E_ARG, "negative dimension at item %d", i);
-        if (dims[i] > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d at item %d exceeds %d", dims[i], i,
-                                               GBS_MAX_DIM);
+        if (dims[i] > gbs::kMaxTileM)
+            return fail(GBS_E_TOO_LARGE, "dimension %d at item %d exceeds %d (batch plans run the register-tile kernels)",
+                        dims[i], i, gbs::kMaxTileM);
         dv[i] = dims[i];
     }
     std::lock_guard<std::mutex> lock(g_mutex);
@@ -583,8 +639,11 @@ gbs_status gbs_batch_plan_create(const int32_t* dims, int32_t count, gbs_precisi
         }
     }
     gbs_z* din = nullptr;
-    HIP_TRY(hipMalloc((void**)&din, sizeof(gbs_z) * hin.size()));
-    HIP_TRY(hipMemcpy(din, hin.data(), sizeof(gbs_z) * hin.size(), hipMemcpyHostToDevice));
+    HIP_TRY(dev_malloc((void**)&din, sizeof(gbs_z) * hin.size()));
+    if (hipMemcpy(din, hin.data(), sizeof(gbs_z) * hin.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(din);
+        return fail(GBS_E_DEVICE, "copy of the tuning batch failed");
+    }
     gbs_plan* best = nullptr;
     float best_ms = 1e30f;
     for (int64_t ts : {1024, 4096, 16384, 65536}) {
@@ -640,7 +699,9 @@ gbs_status gbs_batch_run(gbs_plan* plan, const gbs_z* mats_dev, gbs_z* out_dev, 
         return fail(GBS_E_ARG, "bad batch run arguments");
     std::lock_guard<std::mutex> lock(g_mutex);
     if (hipSetDevice(plan->device) != hipSuccess) return fail(GBS_E_DEVICE, "hipSetDevice failed");
-    return plan_run(plan, mats_dev, out_dev, abs_sum_dev, reinterpret_cast<hipStream_t>(stream));
+    // while per-launch profiling is on, the schedule runs eagerly with every
+    // per-subset launch timed (same launches and arguments as the graph)
+    return plan_run(plan, mats_dev, out_dev, abs_sum_dev, reinterpret_cast<hipStream_t>(stream), true);
 }
 
 void gbs_batch_plan_destroy(gbs_plan* plan) {

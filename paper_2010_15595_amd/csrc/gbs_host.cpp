@@ -48,9 +48,13 @@ uint64_t binom_host(int a, int b) {
 
 int layout_for(const DevCtx* c, int n, int s, bool batch, bool fp32) {
     if (batch) {
-        if (c->layout_multi[n][s] >= 0) return c->layout_multi[n][s];
+        int v = c->layout_multi[n][s];
         // measured slower inside batches than the two-team 8x4 grid
-        if (c->layout[n][s] == gbs::kLayout84T) return gbs::kLayout84;
+        if (v < 0) v = (c->layout[n][s] == gbs::kLayout84T) ? gbs::kLayout84 : c->layout[n][s];
+        if (v < 0) v = gbs::charpoly_default_layout(2 * s);
+        // the persistent 8x4 instances above m = kMaxBatchM84 spill registers
+        if ((v == gbs::kLayout84 || v == gbs::kLayout84T) && 2 * s > gbs::kMaxBatchM84) v = gbs::kLayout88;
+        return v;
     }
     const int v = c->layout[n][s];
     // the tuner times the FP64 kernels; the FP32 La Budde instances of the
@@ -77,6 +81,7 @@ struct ProfRec {
     double flops, subsets;
     std::string kernel;  // instance name of a per-subset launch
 };
+// Both are touched only by calls that hold g_mutex.
 bool g_prof = false;
 std::vector<ProfRec> g_prof_recs;
 
@@ -92,16 +97,33 @@ hipError_t timed_launch(int kind, double flops, double subsets, hipStream_t st, 
     if (!g_prof) return launch();
     ProfRec r{kind, nullptr, nullptr, flops, subsets, kernel};
     hipError_t e = hipEventCreate(&r.a);
-    if (e != hipSuccess) return e;
-    e = hipEventCreate(&r.b);
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(r.a, st);
-    if (e != hipSuccess) return e;
-    e = launch();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(r.b, st);
+    if (e == hipSuccess) e = hipEventCreate(&r.b);
+    if (e == hipSuccess) e = hipEventRecord(r.a, st);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(r.b, st);
+    if (e != hipSuccess) {
+        if (r.a) hipEventDestroy(r.a);
+        if (r.b) hipEventDestroy(r.b);
+        return e;
+    }
     g_prof_recs.push_back(r);
     return e;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+    const char* f = std::getenv("GBS_TEST_FAIL_ALLOC");
+    if (f && f[0] == '1' && f[1] == 0) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+bool profiling_on() { return g_prof; }
+
+hipError_t prof_charpoly_launch(double flops, double subsets, hipStream_t st,
+                                const std::function<hipError_t()>& launch, const std::string& kernel) {
+    return timed_launch(kProfCharpoly, flops, subsets, st, launch, kernel);
 }
 
 gbs_status ensure_buffer(void** p, size_t* cap, size_t need, size_t elem) {
@@ -109,7 +131,7 @@ gbs_status ensure_buffer(void** p, size_t* cap, size_t need, size_t elem) {
     if (*p) hipFree(*p);
     *p = nullptr;
     *cap = 0;
-    hipError_t e = hipMalloc(p, need * elem);
+    hipError_t e = dev_malloc(p, need * elem);
     if (e != hipSuccess) {
         *p = nullptr;
         return fail(GBS_E_NOMEM, "hipMalloc(%zu bytes) failed: %s", need * elem, hipGetErrorString(e));
@@ -117,6 +139,9 @@ gbs_status ensure_buffer(void** p, size_t* cap, size_t need, size_t elem) {
     *cap = need;
     return GBS_OK;
 }
+
+void ctx_destroy(DevCtx* c);
+gbs_status ctx_init(DevCtx* c);
 
 gbs_status ctx_create(int device, DevCtx** out) {
     int count = 0;
@@ -126,6 +151,17 @@ gbs_status ctx_create(int device, DevCtx** out) {
     HIP_TRY(hipSetDevice(device));
     DevCtx* c = new DevCtx();
     c->device = device;
+    const gbs_status st = ctx_init(c);
+    if (st != GBS_OK) {
+        ctx_destroy(c);  // frees whatever was created before the failure
+        return st;
+    }
+    *out = c;
+    return GBS_OK;
+}
+
+gbs_status ctx_init(DevCtx* c) {
+    const int device = c->device;
     HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
     HIP_TRY(hipEventCreate(&c->t0));
@@ -133,16 +169,16 @@ gbs_status ctx_create(int device, DevCtx** out) {
     std::vector<uint64_t> tab(gbs::kBinomStride * gbs::kBinomStride, 0);
     for (int a = 0; a < gbs::kBinomStride; ++a)
         for (int b = 0; b < gbs::kBinomStride; ++b) tab[a * gbs::kBinomStride + b] = binom_host(a, b);
-    HIP_TRY(hipMalloc((void**)&c->binom, tab.size() * sizeof(uint64_t)));
+    HIP_TRY(dev_malloc((void**)&c->binom, tab.size() * sizeof(uint64_t)));
     HIP_TRY(hipMemcpy(c->binom, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     std::vector<int4> lbt(gbs::kLbTableEntries);
     gbs::lb_fill_table(lbt.data());
-    HIP_TRY(hipMalloc((void**)&c->lbmap, lbt.size() * sizeof(int4)));
+    HIP_TRY(dev_malloc((void**)&c->lbmap, lbt.size() * sizeof(int4)));
     HIP_TRY(hipMemcpy(c->lbmap, lbt.data(), lbt.size() * sizeof(int4), hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc((void**)&c->A0, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
-    HIP_TRY(hipMalloc((void**)&c->dvec, sizeof(double2) * GBS_MAX_DIM));
-    HIP_TRY(hipMalloc((void**)&c->Ain, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
-    HIP_TRY(hipMalloc((void**)&c->res, sizeof(double2) * 3));
+    HIP_TRY(dev_malloc((void**)&c->A0, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
+    HIP_TRY(dev_malloc((void**)&c->dvec, sizeof(double2) * GBS_MAX_DIM));
+    HIP_TRY(dev_malloc((void**)&c->Ain, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
+    HIP_TRY(dev_malloc((void**)&c->res, sizeof(double2) * 3));
     HIP_TRY(hipEventRecord(c->done, c->stream));
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
@@ -150,14 +186,15 @@ gbs_status ctx_create(int device, DevCtx** out) {
         for (char* q = c->name; *q; ++q)
             if (*q == ' ' || *q == ':') *q = '_';
     }
-    *out = c;
     return GBS_OK;
 }
 
 void ctx_destroy(DevCtx* c) {
     if (!c) return;
     hipSetDevice(c->device);
-    if (c->stream) hipStreamSynchronize(c->stream);
+    // device-pointer calls run on the callers' streams and read the context's
+    // tables and workspace: let all of them finish first
+    hipDeviceSynchronize();
     hipFree(c->binom);
     hipFree(c->lbmap);
     hipFree(c->A0);
@@ -358,6 +395,23 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
         const double sign = ((n - s) & 1) ? -1.0 : 1.0;
         for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
             const uint64_t len = std::min(kChunk, cnt - st0);
+            if (2 * s > gbs::kMaxTileM) {
+                // beyond the register tiles: the LDS-resident FP64 kernel writes the
+                // signed terms, a block reduction folds them into the same partials
+                HIP_TRY(timed_launch(
+                    kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
+                    [&] {
+                        return gbs::launch_charpoly_lds(0, gbs::kCharpolyLaBudde, c->A0, c->dvec, Np, s, st0, len,
+                                                        nullptr, c->binom, D, sign, c->E, st);
+                    },
+                    "charpoly_lds_kernel<ArF64, 0>"));
+                HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, st, [&] {
+                    return gbs::launch_lds_block_reduce(0, c->E, len, kPerThread, c->partials + 5 * poff, nullptr, st);
+                }));
+                poff += (len + per_block - 1) / per_block;
+                nl += 2;
+                continue;
+            }
             gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, c->E, fp32 ? 1 : 0, c->lbmap};
             const int lay = layout_for(c, n, s, false, fp32);
             HIP_TRY(timed_launch(
@@ -794,11 +848,12 @@ gbs_status gbs_lhaf_terms(const gbs_z* A, int32_t N, int64_t lda, const uint64_t
             const size_t len = std::min<size_t>(kChunk, grp.size() - off);
             st = ensure_buffer((void**)&c->masks, &c->masks_cap, len, sizeof(uint64_t));
             if (st != GBS_OK) return st;
-            if (c->terms) hipFree(c->terms);
-            c->terms = nullptr;
-            HIP_TRY(hipMalloc((void**)&c->terms, sizeof(double2) * len));
+            st = ensure_buffer((void**)&c->terms, &c->terms_cap, len, sizeof(double2));
+            if (st != GBS_OK) return st;
+            const bool lds_route = !dd && 2 * s > gbs::kMaxTileM;
             const size_t ebytes = dd ? len * 4 * sizeof(double)
-                                     : len * 2 * (D + 1) * (fp32 ? sizeof(float2) : sizeof(double2));
+                                     : len * std::max<size_t>(2 * (D + 1) * (fp32 ? sizeof(float2) : sizeof(double2)),
+                                                              gbs::lds_term_bytes(0));
             st = ensure_buffer(&c->E, &c->E_cap, ebytes, 1);
             if (st != GBS_OK) return st;
             const size_t nblk = (len + 64 * kPerThread - 1) / (64 * kPerThread);
@@ -810,6 +865,10 @@ gbs_status gbs_lhaf_terms(const gbs_z* A, int32_t N, int64_t lda, const uint64_t
                 HIP_TRY(gbs::launch_charpoly_dd(c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, sign, c->E,
                                                 c->stream));
                 HIP_TRY(gbs::launch_dd_block_reduce(c->E, len, kPerThread, c->partials, c->terms, c->stream));
+            } else if (lds_route) {
+                HIP_TRY(gbs::launch_charpoly_lds(0, gbs::kCharpolyLaBudde, c->A0, c->dvec, Np, s, 0, len, c->masks,
+                                                 c->binom, D, sign, c->E, c->stream));
+                HIP_TRY(gbs::launch_lds_block_reduce(0, c->E, len, kPerThread, c->partials, c->terms, c->stream));
             } else {
                 gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, 0, len, c->masks, c->binom, D, c->E, fp32 ? 1 : 0,
                                      c->lbmap};
@@ -1085,14 +1144,15 @@ gbs_status gbs_selftest(int32_t* failures) {
     double hin[64], hout[1152];
     for (int l = 0; l < 64; ++l) hin[l] = std::ldexp(1.0, l % 20) + 0.25 * l;
     double *din = nullptr, *dout = nullptr;
-    HIP_TRY(hipMalloc((void**)&din, sizeof hin));
-    HIP_TRY(hipMalloc((void**)&dout, sizeof hout));
-    HIP_TRY(hipMemcpy(din, hin, sizeof hin, hipMemcpyHostToDevice));
-    HIP_TRY(gbs::launch_selftest(din, dout, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    HIP_TRY(hipMemcpy(hout, dout, sizeof hout, hipMemcpyDeviceToHost));
+    hipError_t e = dev_malloc((void**)&din, sizeof hin);
+    if (e == hipSuccess) e = dev_malloc((void**)&dout, sizeof hout);
+    if (e == hipSuccess) e = hipMemcpy(din, hin, sizeof hin, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = gbs::launch_selftest(din, dout, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(hout, dout, sizeof hout, hipMemcpyDeviceToHost);
     hipFree(din);
     hipFree(dout);
+    HIP_TRY(e);
     int bad = 0;
     for (int l = 0; l < 64; ++l) {
         double so = 0.0, ss = 0.0;

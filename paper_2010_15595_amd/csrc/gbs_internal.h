@@ -53,7 +53,7 @@ struct DevCtx {
     size_t partials_cap = 0;    // partial records
     uint64_t* masks = nullptr;
     double2* terms = nullptr;
-    size_t masks_cap = 0;
+    size_t masks_cap = 0, terms_cap = 0;
     BatchRunner* runner = nullptr;  // eager batch runner of the sampling chain, created on first use
     void* smats = nullptr;          // packed loop-hafnian matrices of one sampling step
     size_t smats_cap = 0;           // bytes
@@ -83,6 +83,10 @@ int layout_for(const DevCtx* c, int n, int s, bool batch = false, bool fp32 = fa
 // so it is called before the caller's matrix is prepared).
 gbs_status maybe_tune(DevCtx* c, int n);
 gbs_status ensure_buffer(void** p, size_t* cap, size_t need, size_t elem);
+// Every device allocation of the library goes through here.  Test hook for the
+// out-of-memory paths: while the environment variable GBS_TEST_FAIL_ALLOC is
+// "1", it fails (nullptr, hipErrorOutOfMemory) without allocating.
+hipError_t dev_malloc(void** p, size_t bytes);
 // Times each valid lane grid per subset size of an n-pair loop hafnian.
 gbs_status autotune_impl(DevCtx* c, int n, gbs_tune_report* rep);
 
@@ -93,6 +97,8 @@ struct CharpolyLaunch {
     int round, layout, s_rep, inst, variant;
     int tile_begin, ntiles;  // range in the device tile array
     int counter;
+    double flops = 0.0, subsets = 0.0;  // yardstick flops and subsets of its tiles
+    std::string kernel;                 // kernel instance name (as the profiler prints it)
 };
 // One series launch (all blocks of one round and one n).
 struct SeriesLaunch {
@@ -141,14 +147,25 @@ struct BatchDev {
     double2* out = nullptr;
     double* abs = nullptr;
     int* small = nullptr;
+    const uint64_t* binom = nullptr;  // binomial table (kBinomStride^2)
+    const int4* lbmap = nullptr;      // La Budde lane maps (gbs::lb_fill_table)
 };
 constexpr int kBatchBranches = 4;  // parallel streams of the per-subset launches of one round
 // Issues the whole schedule: counter fill, prep, rounds of per-subset launches
 // on the branch streams (joined into `cs` through events from `new_event`),
 // series launches and the per-item reduction, all ordered after prior work on
 // `cs`.  Works eagerly and under stream capture alike.
+// With `prof`, per-subset launches are timed when gbs_profile_enable is on
+// (never under stream capture).
 gbs_status batch_enqueue(DevCtx* c, const BatchSchedule& S, const BatchDev& d, hipStream_t cs, hipStream_t* br,
-                         const std::function<hipError_t(hipEvent_t*)>& new_event);
+                         const std::function<hipError_t(hipEvent_t*)>& new_event, bool prof);
+
+// Per-launch timing (gbs_profile_*): true while profiling is on.
+bool profiling_on();
+// Runs `launch`; while profiling is on, brackets it with a HIP event pair on
+// `st`, recorded as a per-subset kernel launch of instance `kernel`.
+hipError_t prof_charpoly_launch(double flops, double subsets, hipStream_t st,
+                                const std::function<hipError_t()>& launch, const std::string& kernel);
 
 // Eager runner of batch schedules on reusable, growing device buffers, for
 // callers whose batches change from one run to the next.

@@ -203,7 +203,7 @@ struct ChainDev {
 
 template <class T>
 gbs_status dalloc(T** p, size_t n) {
-    const hipError_t e = hipMalloc((void**)p, std::max<size_t>(1, n) * sizeof(T));
+    const hipError_t e = dev_malloc((void**)p, std::max<size_t>(1, n) * sizeof(T));
     if (e != hipSuccess) {
         *p = nullptr;
         return fail(GBS_E_NOMEM, "hipMalloc(%zu) failed: %s", n * sizeof(T), hipGetErrorString(e));
@@ -226,7 +226,7 @@ extern "C" gbs_status gbs_sample_pure(const gbs_z* Q, const gbs_z* alpha, int32_
     if (prec == GBS_DD) return fail(GBS_E_UNSUPPORTED, "the sampling chain runs in FP64 or FP32_COMP");
     if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
     if (M > gbs::kMaxSamplerModes) return fail(GBS_E_TOO_LARGE, "%d modes exceed %d", M, gbs::kMaxSamplerModes);
-    if (cutoff > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "cutoff %d exceeds %d", cutoff, GBS_MAX_DIM);
+    if (cutoff > gbs::kMaxTileM) return fail(GBS_E_TOO_LARGE, "cutoff %d exceeds %d", cutoff, gbs::kMaxTileM);
     for (int64_t i = 0; i < (int64_t)nsamples * 2 * (M - 1); ++i)
         if (!std::isfinite(normals[i])) return fail(GBS_E_NONFINITE, "non-finite normal %lld", (long long)i);
     for (int64_t i = 0; i < (int64_t)nsamples * M; ++i)
@@ -283,12 +283,12 @@ extern "C" gbs_status gbs_sample_pure(const gbs_z* Q, const gbs_z* alpha, int32_
         for (int k = 1; k <= M; ++k) {
             dims.resize((size_t)G * K1);
             for (int b = 0; b < G; ++b) {
-                if (P_tot[b] + cutoff > GBS_MAX_DIM) {
+                if (P_tot[b] + cutoff > gbs::kMaxTileM) {
                     HIP_TRY(hipStreamSynchronize(s));
                     return fail(GBS_E_TOO_LARGE,
                                 "sample %d holds %d photons before mode %d: its loop hafnians up to cutoff %d "
                                 "exceed dimension %d",
-                                g0 + b, P_tot[b], k, cutoff, GBS_MAX_DIM);
+                                g0 + b, P_tot[b], k, cutoff, gbs::kMaxTileM);
                 }
                 for (int j = 0; j < K1; ++j) dims[(size_t)b * K1 + j] = P_tot[b] + j;
             }

@@ -581,15 +581,6 @@ __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, 
     }
 }
 
-// Wavefronts per SIMD the register allocation of each instance is held to.
-#ifdef GBS_WPE_FORCE
-__host__ __device__ constexpr int charpoly_waves_per_simd(int, int, int, int, bool) { return GBS_WPE_FORCE; }
-#else
-__host__ __device__ constexpr int charpoly_waves_per_simd(int P, int Q, int MR, int MC, bool batch) {
-    return 1;
-}
-#endif
-
 // One wavefront's work: the W subsets with local indices first .. first+W-1
 // of a run of `count` subsets of size s (colex ranks rank0 + index, or the
 // explicit masks), each written to Eout + index * 2(D+1).
@@ -597,7 +588,12 @@ __host__ __device__ constexpr int charpoly_waves_per_simd(int P, int Q, int MR, 
 // the FP64 path, float2 for the FP32 path; the Hessenberg reduction is FP64).
 // La Budde teams have TEAM lanes (P Q, or 64 when a subset needs more than
 // P Q coefficient lanes), fixed per launch; lbm is the lane map of (TEAM, D).
-template <int P, int Q, int MR, int MC, class V, int TEAM, int O = 0>
+// LOOPED: the caller runs this in a loop (persistent kernels).  The lane index
+// is then passed through an empty asm statement, so the compiler cannot hoist
+// the lane-dependent index and predicate arithmetic of the body out of the
+// loop and keep it live across iterations (that costs 40-70 VGPRs and
+// halves the occupancy of the persistent kernels).
+template <int P, int Q, int MR, int MC, class V, int TEAM, int O = 0, bool LOOPED = false>
 __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, const double2* __restrict__ dvec, int Np,
                                               int s, uint64_t rank0, uint64_t count, uint64_t first,
                                               const uint64_t* __restrict__ masks, const uint64_t* __restrict__ binom,
@@ -606,7 +602,8 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     constexpr int T = TEAM;
     constexpr int G = P * Q;
     constexpr int W = 64 / G;
-    const int lane = threadIdx.x;
+    int lane = threadIdx.x;
+    if constexpr (LOOPED) asm volatile("" : "+v"(lane));
     const int g = lane / G;
     const int pr = lane % P;
     const int pc = (lane / P) % Q;
@@ -770,7 +767,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
 
 
 template <int P, int Q, int MR, int MC, class V, int TEAM, int O>
-__global__ void __launch_bounds__(64, charpoly_waves_per_simd(P, Q, MR, MC, false))
+__global__ void __launch_bounds__(64)
     charpoly_kernel(const double2* __restrict__ A0, const double2* __restrict__ dvec, int Np, int s, uint64_t rank0,
                     uint64_t count, const uint64_t* __restrict__ masks, const uint64_t* __restrict__ binom, int D,
                     const int4* __restrict__ lbm, V* __restrict__ Eout) {
@@ -784,7 +781,7 @@ __global__ void __launch_bounds__(64, charpoly_waves_per_simd(P, Q, MR, MC, fals
 // (largest first) through a device counter until none is left, and runs all
 // subsets of each tile.  The counter is cleared by the caller's fill kernel.
 template <int P, int Q, int MR, int MC, class V, int TEAM>
-__global__ void __launch_bounds__(64, charpoly_waves_per_simd(P, Q, MR, MC, true)) charpoly_batch_kernel(const BatchTile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(64) charpoly_batch_kernel(const BatchTile* __restrict__ tiles, int ntiles,
                                                             const BatchItem* __restrict__ items,
                                                             const uint64_t* __restrict__ binom,
                                                             const int4* __restrict__ lbmap,
@@ -805,8 +802,8 @@ __global__ void __launch_bounds__(64, charpoly_waves_per_simd(P, Q, MR, MC, true
         if (TEAM < D + 1) continue;  // a team must hold D + 1 coefficients; the plan never sends such tiles
         const int4* lbm = lbmap + lb_table_offset(TEAM, D);
         for (uint64_t first = 0; first < tl.count; first += W)
-            charpoly_wave<P, Q, MR, MC, V, TEAM>(it.A0, it.dvec, it.Np, tl.s, tl.rank0, tl.count, first, nullptr,
-                                                 binom, D, lbm, Ebase + tl.eoff, lds);
+            charpoly_wave<P, Q, MR, MC, V, TEAM, 0, true>(it.A0, it.dvec, it.Np, tl.s, tl.rank0, tl.count, first,
+                                                          nullptr, binom, D, lbm, Ebase + tl.eoff, lds);
         wave_sync();
     }
 }

@@ -14,9 +14,26 @@ constexpr int kBinomStride = 33;    // binomial table C(a, b), 0 <= a, b <= 32
 // columns put their spare rows and columns in front (offset 2, 4 or 6 on
 // 8-column grids, 2 on 4-column grids), which shortens the first Householder
 // phase; smaller tiles, and every batch launch, keep them behind (offset 0).
+// The offsets of two tile shapes stay 0 because those instances would spill
+// registers: offset 2 with seven local columns on 8-column grids, and any
+// offset with nine or ten local columns on 4-column grids.
 __host__ __device__ constexpr int charpoly_front_offset(int P, int Q, int MR, int MC, int m) {
-    return (MC >= 3) ? ((P * MR < Q * MC ? P * MR : Q * MC) - m) : 0;
+    const int o = (MC >= 3) ? ((P * MR < Q * MC ? P * MR : Q * MC) - m) : 0;
+    if (Q == 8 && MC == 7 && o == 2) return 0;
+    if (Q == 4 && MC >= 9) return 0;
+    return o;
 }
+
+// Largest subset matrix (m = 2s) the register-tile kernels take.  An 8 x 8
+// tile of complex values per lane (m = 57..64) does not fit the register file
+// without scratch spills; those subsets, at most C(32, 29) + C(32, 30) +
+// C(32, 31) + 1 = 5489 of the 2^32 of an N = 64 loop hafnian, run on the
+// LDS-resident FP64 kernel (launch_charpoly_lds) instead, and batch plans
+// take items up to N = kMaxTileM.
+constexpr int kMaxTileM = 56;
+// Largest m on the 8 x 4 grid inside batch plans (its nine- and ten-column
+// persistent instances spill).
+constexpr int kMaxBatchM84 = 32;
 
 // Phase 1: one wavefront per pair subset of size s; writes, per subset, the
 // D + 1 leading coefficients of det(xI - C) then of det(xI - C').

@@ -396,7 +396,7 @@ bool charpoly_layout_ok(int m, int layout) {
     switch (layout) {
         case kLayout44: return m <= 24;
         case kLayout84: return m <= 40;
-        case kLayout88: return m <= 64;
+        case kLayout88: return m <= kMaxTileM;
         case kLayout84T: return m <= 40;
     }
     return false;
@@ -481,6 +481,7 @@ hipError_t launch_charpoly_batch(int layout, int s_rep, int variant, int D_max, 
                                  int ntiles, const BatchItem* items, const uint64_t* binom, const int4* lbmap,
                                  unsigned* counter, void* Ebase, int grid, hipStream_t st) {
     if (!charpoly_layout_ok(2 * s_rep, layout)) return hipErrorInvalidValue;
+    if ((layout == kLayout84 || layout == kLayout84T) && 2 * s_rep > kMaxBatchM84) return hipErrorInvalidValue;
     switch (layout) {
         case kLayout44:
             return launch_charpoly_batch_l44(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
@@ -596,19 +597,19 @@ __global__ void __launch_bounds__(64) small_items_kernel(const int* __restrict__
             for (uint64_t first = 0; first < cnt; first += W) {
                 switch (mr) {
                     case 1:
-                        charpoly_wave<4, 4, 1, 1, double2, 16>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
+                        charpoly_wave<4, 4, 1, 1, double2, 16, 0, true>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
                                                                binom, D, lbm, E, lds);
                         break;
                     case 2:
-                        charpoly_wave<4, 4, 2, 2, double2, 16>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
+                        charpoly_wave<4, 4, 2, 2, double2, 16, 0, true>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
                                                                binom, D, lbm, E, lds);
                         break;
                     case 3:
-                        charpoly_wave<4, 4, 3, 3, double2, 16>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
+                        charpoly_wave<4, 4, 3, 3, double2, 16, 0, true>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
                                                                binom, D, lbm, E, lds);
                         break;
                     default:
-                        charpoly_wave<4, 4, 4, 4, double2, 16>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
+                        charpoly_wave<4, 4, 4, 4, double2, 16, 0, true>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
                                                                binom, D, lbm, E, lds);
                         break;
                 }

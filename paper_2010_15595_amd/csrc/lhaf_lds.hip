@@ -23,7 +23,7 @@ namespace {
 
 constexpr int kLdsThreads = 256;
 constexpr int kSlices = kLdsThreads / 64;  // row / term slices of the dot products
-constexpr int kScratch = 448;              // complex slots shared by the phases
+constexpr int kScratch = 456;              // complex slots shared by the phases
 constexpr int kMaxQrSweeps = 30;           // per eigenvalue, before the subset is marked failed
 
 __device__ __forceinline__ double shfl_xor_dbl(double x, int m) {
@@ -334,8 +334,8 @@ __global__ void __launch_bounds__(kLdsThreads) charpoly_lds_kernel(const double2
     // ---- Householder Hessenberg reduction of C' ----
     C* v = scr;          // 64: reflector
     C* v2 = scr + 64;    // 64: tau v
-    C* part = scr + 128; // kSlices x 64
-    C* w = scr + 128 + kSlices * 64;  // 64
+    C* part = scr + 128; // kSlices x 65 (row partials; K <= 65 rows)
+    C* w = scr + 128 + kSlices * 65;  // 65
     for (int c = 0; c + 2 < K; ++c) {
         const int L = K - c - 1;  // rows / columns c+1..K-1
         if (slice == 0) {
@@ -386,17 +386,17 @@ __global__ void __launch_bounds__(kLdsThreads) charpoly_lds_kernel(const double2
             h = Ar::sub(h, Ar::mul(v2[i], w[j]));
         }
         __syncthreads();
-        // right: u_i = sum_j H[i][c+1+j] v_j over all rows i
-        if (lane < K) {
+        // right: u_i = sum_j H[i][c+1+j] v_j over all rows i (K <= 65: lane l takes rows l and l + 64)
+        for (int i = lane; i < K; i += 64) {
             C acc = Ar::zero();
-            for (int j = slice; j < L; j += kSlices) acc = Ar::add(acc, Ar::mul(H[lane * K + c + 1 + j], v[j]));
-            part[slice * 64 + lane] = acc;
+            for (int j = slice; j < L; j += kSlices) acc = Ar::add(acc, Ar::mul(H[i * K + c + 1 + j], v[j]));
+            part[slice * 65 + i] = acc;
         }
         __syncthreads();
-        if (t < K) {
-            C acc = part[t];
-            for (int q = 1; q < kSlices; ++q) acc = Ar::add(acc, part[q * 64 + t]);
-            w[t] = acc;
+        for (int i = t; i < K; i += kLdsThreads) {
+            C acc = part[i];
+            for (int q = 1; q < kSlices; ++q) acc = Ar::add(acc, part[q * 65 + i]);
+            w[i] = acc;
         }
         __syncthreads();
         for (int e = t; e < K * L; e += kLdsThreads) {
@@ -626,7 +626,7 @@ hipError_t launch_charpoly_lds(int prec_dd, int method, const double2* A0, const
     if (s < 1 || maxp == 0 || m > 2 * maxp || D < 2 || D > maxp + 1 || count > (uint64_t)INT32_MAX)
         return hipErrorInvalidValue;
     static_assert(kScratch >= 384 + 64, "series scratch");
-    static_assert(kScratch >= 128 + kSlices * 64 + 64, "Householder scratch");
+    static_assert(kScratch >= 128 + kSlices * 65 + 65, "Householder scratch");
     const size_t lds = lds_bytes(m, D, prec_dd, method), lds_max = lds_bytes(2 * maxp, maxp + 1, prec_dd, method);
     if (lds_max > 160 * 1024) return hipErrorInvalidValue;
     if (prec_dd)

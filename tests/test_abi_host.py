@@ -40,6 +40,10 @@ def test_status_strings():
 
 def test_max_dim():
     assert gbs.max_dim() == 64
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define (GBS_MAX_\w+) (\d+)", text))
+    assert int(defs["GBS_MAX_DIM"]) == gbs.MAX_DIM == gbs.max_dim()
+    assert int(defs["GBS_MAX_BATCH_DIM"]) == gbs.MAX_BATCH_DIM
 
 
 def test_no_device_reports_device_error():

@@ -3,8 +3,14 @@ against single evaluations and the oracle, including graph replays."""
 import numpy as np
 import pytest
 
+import os
+import sys
+
 import oracle
 from paper_2010_15595_amd import workloads
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import make_lhaf_refs  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -150,14 +156,30 @@ def test_batch_with_one_team_layout(gbs):
 
 def test_full_size_chain_workload(gbs):
     """The 4096-item chain-like workload the batch benchmark replays, in the
-    same plan configuration: sampled items (the largest among them) against
-    single evaluations, and the items with N <= 16 among them against the oracle."""
+    same plan configuration: one item of every N in 22..36 and the eight
+    largest against the long-double oracle (stored full sums, which run on the
+    persistent kernels); sampled items against single evaluations, and the
+    items with N <= 16 among them against the oracle."""
     st = workloads.config4(count=4096)
     mats = [gbs.expand(st["B"], st["gamma"], pat) for pat in st["patterns"]]
     dims = [a.shape[0] for a in mats]
     plan = gbs.BatchPlan(dims)
     got, ab = _run(gbs, plan, mats)
     plan.close()
+    refs = make_lhaf_refs.load()
+    picks = make_lhaf_refs.c4_picks(dims)
+    assert sorted({dims[i] for i in picks}) == list(range(22, 37, 2))
+    worst_ld = 0.0
+    for i in picks:
+        Nr, re, im, ab_ref = refs[f"c4_{i}"]
+        assert Nr == dims[i]
+        ref = complex(float(re), float(im))
+        err = abs(got[i] - ref)
+        assert ab[i] == pytest.approx(float(ab_ref), rel=1e-12), i
+        assert err <= max(1e-10 * abs(ref), NORMWISE * float(ab_ref)), (i, dims[i], err / float(ab_ref))
+        worst_ld = max(worst_ld, err / float(ab_ref))
+    print(f"[batch 4096] {len(picks)} items N=22..36 vs long-double oracle: worst |err|/sum|t| {worst_ld:.2e}",
+          flush=True)
     order = np.argsort(dims)
     pick = sorted(set([int(i) for i in order[-8:]] + [int(i) for i in order[:8]] +
                       [int(i) for i in np.random.default_rng(1).choice(len(mats), 16, replace=False)]))
@@ -171,3 +193,16 @@ def test_full_size_chain_workload(gbs):
             assert abs(got[i] - ref) <= max(1e-10 * abs(ref), NORMWISE * ab[i]), (i, dims[i])
     print(f"[batch 4096] {len(pick)} sampled items, N {min(dims)}..{max(dims)}, worst |batch-single|/sum|t| "
           f"{worst:.2e}", flush=True)
+
+
+def test_plan_survives_finalize(gbs):
+    """A plan owns its copies of the library tables: run, gbs_finalize,
+    gbs_init, run again gives identical results."""
+    dims, mats = _items(12, seed=11, lo=10, hi=30)
+    plan = gbs.BatchPlan(dims)
+    first, _ = _run(gbs, plan, mats)
+    gbs.finalize()
+    gbs.init(0)
+    again, _ = _run(gbs, plan, mats)
+    plan.close()
+    assert np.array_equal(first, again)

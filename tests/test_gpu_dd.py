@@ -85,6 +85,8 @@ def test_benchmark_family_agrees_with_long_double(gbs):
     # the long-double oracle's own error (unit roundoff 5.4e-20, about 2000 times below FP64's)
     assert e_ld < 1e-17
     assert e_ld < e_64 / 20
+    # the FP64 path against the dd value: the normwise FP64 gate (reading R6)
+    assert e_64 <= 2e-14
 
     # a permutation changes every subset's rounding but not the value
     rng = np.random.default_rng(7)
