@@ -39,6 +39,8 @@ extern "C" {
 /* Batch plans and the sampling chain run only the register-tile kernels, whose
  * largest tile holds a 56 x 56 subset matrix without register spills. */
 #define GBS_MAX_BATCH_DIM 56
+/* Size of the fixed per-device scratch array of gbs_lhaf_device_noalloc. */
+#define GBS_NOALLOC_SCRATCH_BYTES (32 << 20)
 
 typedef struct { double re, im; } gbs_z;
 
@@ -191,6 +193,26 @@ gbs_status gbs_lhaf_terms(const gbs_z *A, int32_t N, int64_t lda, const uint64_t
  * `stream` (a hipStream_t, NULL = null stream); asynchronous. */
 gbs_status gbs_lhaf_device(const gbs_z *A_dev, int32_t N, gbs_precision prec, gbs_z *out_dev,
                            double *abs_sum_dev, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * loop hafnian as gbs_lhaf_device (same arguments, device pointers, ordered on
+ * `stream`, asynchronous) with no allocation, no freeing and no autotuning in
+ * the call.  Every buffer beyond the caller's input and outputs lives in one
+ * fixed device array of GBS_NOALLOC_SCRATCH_BYTES (32 MiB) per device, which
+ * the library holds until the process ends; it keeps the last call's
+ * contents, and every value a call reads from it is written by that call
+ * first.  gbs_init(device) must have been called for the current device
+ * (GBS_E_ARG otherwise).  N <= GBS_MAX_DIM (GBS_E_TOO_LARGE above);
+ * GBS_FP64 or GBS_FP32_COMP (GBS_E_UNSUPPORTED for GBS_DD).  Lane grids are
+ * those of earlier tuning or gbs_set_layout, else the defaults.  All calls on
+ * one device share the array: calls that overlap in time on one GPU (on
+ * different streams, or from several threads with their streams running
+ * concurrently) race and give wrong results.  The result agrees with
+ * gbs_lhaf_device to rounding: the sum is folded per chunk of subsets, a
+ * different order of the same compensated additions. */
+gbs_status gbs_lhaf_device_noalloc(const gbs_z *A_dev, int32_t N, gbs_precision prec, gbs_z *out_dev,
+                                   double *abs_sum_dev, void *stream);
 
 /* ---- batches of loop hafnians: plan once, replay many times -------------- */
 

@@ -23,6 +23,7 @@ from ._lib import (  # noqa: F401
     init,
     lhaf,
     lhaf_device,
+    lhaf_device_noalloc,
     lhaf_method,
     lhaf_terms,
     lib,

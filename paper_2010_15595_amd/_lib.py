@@ -131,6 +131,8 @@ def lib():
         L.gbs_lhaf_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]
         L.gbs_lhaf_device.restype = st
+        L.gbs_lhaf_device_noalloc.argtypes = L.gbs_lhaf_device.argtypes
+        L.gbs_lhaf_device_noalloc.restype = st
         L.gbs_selftest.argtypes = [I32P]
         L.gbs_selftest.restype = st
         L.gbs_profile_enable.argtypes = [ctypes.c_int]
@@ -335,6 +337,26 @@ def lhaf_device(A, out, abs_sum=None, stream=None, prec=GBS_FP64):
     _check(lib().gbs_lhaf_device(ctypes.c_void_p(A.data_ptr()), N, prec, ctypes.c_void_p(out.data_ptr()),
                                  ctypes.c_void_p(abs_sum.data_ptr()) if abs_sum is not None else None,
                                  ctypes.c_void_p(stream.cuda_stream)))
+
+
+def lhaf_device_noalloc(A, out, abs_sum=None, stream=None, prec=GBS_FP64):
+    """lhaf_device through the entry point that allocates nothing (its scratch
+    is a fixed per-device array; init() must come first).  Calls on one device
+    must not overlap in time."""
+    import torch
+
+    if A.dtype != torch.complex128 or not A.is_cuda or not A.is_contiguous():
+        raise ValueError("A must be a contiguous complex128 device tensor")
+    if out.dtype != torch.complex128 or not out.is_cuda:
+        raise ValueError("out must be a complex128 device tensor")
+    if abs_sum is not None and (abs_sum.dtype != torch.float64 or not abs_sum.is_cuda):
+        raise ValueError("abs_sum must be a float64 device tensor")
+    N = A.shape[0]
+    if stream is None:
+        stream = torch.cuda.current_stream(A.device)
+    _check(lib().gbs_lhaf_device_noalloc(ctypes.c_void_p(A.data_ptr()), N, prec, ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(abs_sum.data_ptr()) if abs_sum is not None else None,
+                                         ctypes.c_void_p(stream.cuda_stream)))
 
 
 def selftest():

@@ -19,7 +19,7 @@ COMMON = [
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result",
 ]
 SOURCES = ["charpoly_l88.hip", "charpoly_l84.hip", "charpoly_l44.hip", "lhaf_kernels.hip", "gbs_host.cpp", "gbs_batch.cpp",
-           "sampler_kernels.hip", "gbs_sampler.cpp", "lhaf_lds.hip"]
+           "sampler_kernels.hip", "gbs_sampler.cpp", "lhaf_lds.hip", "gbs_noalloc.cpp"]
 
 
 def _compile(src):

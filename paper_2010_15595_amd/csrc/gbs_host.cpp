@@ -180,6 +180,8 @@ gbs_status ctx_init(DevCtx* c) {
     HIP_TRY(dev_malloc((void**)&c->Ain, sizeof(double2) * GBS_MAX_DIM * GBS_MAX_DIM));
     HIP_TRY(dev_malloc((void**)&c->res, sizeof(double2) * 3));
     HIP_TRY(hipEventRecord(c->done, c->stream));
+    const gbs_status na = noalloc_setup(c);
+    if (na != GBS_OK) return na;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
         snprintf(c->name, sizeof c->name, "%s", prop.gcnArchName);
@@ -212,6 +214,11 @@ void ctx_destroy(DevCtx* c) {
     if (c->t1) hipEventDestroy(c->t1);
     if (c->stream) hipStreamDestroy(c->stream);
     delete c;
+}
+
+DevCtx* existing_ctx(int dev) {
+    auto it = g_ctx.find(dev);
+    return it == g_ctx.end() ? nullptr : it->second;
 }
 
 // Context of the current HIP device, created on first use.

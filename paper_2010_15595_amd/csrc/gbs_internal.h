@@ -57,6 +57,7 @@ struct DevCtx {
     BatchRunner* runner = nullptr;  // eager batch runner of the sampling chain, created on first use
     void* smats = nullptr;          // packed loop-hafnian matrices of one sampling step
     size_t smats_cap = 0;           // bytes
+    void* na_scratch = nullptr;     // device address of this device's no-allocation scratch array
     // lane grid per (n, s); -1 = heuristic default.  layout_multi is the
     // choice for batch plans, where many launches share the device: the
     // tuner's best among the grids with one La Budde team per subset group
@@ -76,6 +77,11 @@ struct DevCtx {
 extern std::mutex g_mutex;  // serialises every library call
 
 gbs_status current_ctx(DevCtx** out);
+// Context of device `dev` if gbs_init (or an earlier call) created it, else
+// nullptr; never creates one (caller holds g_mutex).
+DevCtx* existing_ctx(int dev);
+// Looks up this device's no-allocation scratch array (gbs_noalloc.cpp).
+gbs_status noalloc_setup(DevCtx* c);
 // Lane grid of subsets of size s of an n-pair loop hafnian; batch = true
 // gives the batch-plan choice.
 int layout_for(const DevCtx* c, int n, int s, bool batch = false, bool fp32 = false);

@@ -178,6 +178,8 @@ hipError_t launch_sampler_draw(const double2* lh, int nsamples, int cutoff, cons
                                int64_t probs_stride, hipStream_t st);
 hipError_t launch_series(int n, const LaunchPhase2& p, hipStream_t st);
 hipError_t launch_final_reduce(const double* partials, int64_t np, double2* out, double* abs_out, hipStream_t st);
+// One partial record (5 doubles) from np records, same fixed order as launch_final_reduce.
+hipError_t launch_partials_fold(const double* partials, int64_t np, double* record, hipStream_t st);
 hipError_t launch_prep(const double2* A, int N, int64_t lda, int Np, double2* A0, double2* d, hipStream_t st);
 hipError_t launch_scalar_set(double2* out, double2 v, double* abs_out, double a, hipStream_t st);
 hipError_t launch_selftest(const double* in, double* out, hipStream_t st);

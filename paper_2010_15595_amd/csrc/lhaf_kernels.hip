@@ -339,6 +339,39 @@ __global__ void __launch_bounds__(256) final_reduce_kernel(const double* __restr
     }
 }
 
+// Folds np partial records into one record (sum, compensation, sum|t|) in the
+// same layout, with the tree of final_reduce_kernel.
+__global__ void __launch_bounds__(256) partials_fold_kernel(const double* __restrict__ partials, int64_t np,
+                                                            double* __restrict__ record) {
+    __shared__ double sh[5][256];
+    const int t = threadIdx.x;
+    Acc A{0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = t; i < np; i += 256) {
+        Acc B{partials[5 * i], partials[5 * i + 1], partials[5 * i + 2], partials[5 * i + 3], partials[5 * i + 4]};
+        acc_merge(A, B);
+    }
+    sh[0][t] = A.sr;
+    sh[1][t] = A.cr;
+    sh[2][t] = A.si;
+    sh[3][t] = A.ci;
+    sh[4][t] = A.ab;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) {
+            Acc X{sh[0][t], sh[1][t], sh[2][t], sh[3][t], sh[4][t]};
+            Acc Y{sh[0][t + w], sh[1][t + w], sh[2][t + w], sh[3][t + w], sh[4][t + w]};
+            acc_merge(X, Y);
+            sh[0][t] = X.sr;
+            sh[1][t] = X.cr;
+            sh[2][t] = X.si;
+            sh[3][t] = X.ci;
+            sh[4][t] = X.ab;
+        }
+        __syncthreads();
+    }
+    if (t < 5) record[t] = sh[t][0];
+}
+
 // A (N x N, leading dim lda) -> A0 (Np x Np, zero diagonal) and d (Np); an odd
 // N gets one extra vertex with loop weight 1 and no edges.
 __global__ void __launch_bounds__(256) prep_kernel(const double2* __restrict__ A, int N, int64_t lda, int Np,
@@ -711,6 +744,11 @@ hipError_t launch_series(int n, const LaunchPhase2& p, hipStream_t st) { return 
 
 hipError_t launch_final_reduce(const double* partials, int64_t np, double2* out, double* abs_out, hipStream_t st) {
     hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(256), 0, st, partials, np, out, abs_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_partials_fold(const double* partials, int64_t np, double* record, hipStream_t st) {
+    hipLaunchKernelGGL(partials_fold_kernel, dim3(1), dim3(256), 0, st, partials, np, record);
     return hipGetLastError();
 }
 
