@@ -165,6 +165,13 @@ __device__ __forceinline__ uint64_t unrank_colex(uint64_t rank, int n, int s, co
     return mask;
 }
 
+// The s-subset following `mask` in colexicographic order (the next larger
+// integer with the same number of set bits; Gosper's successor).  mask != 0.
+__device__ __forceinline__ uint64_t colex_next(uint64_t mask) {
+    const uint64_t ripple = mask + (mask & (~mask + 1ull));
+    return ripple | (((ripple ^ mask) >> 2) >> __builtin_ctzll(mask));
+}
+
 // ---------------------------------------------------------------- phase 1
 
 // Lane grids.  A wavefront holds W = 64 / (P Q) subsets of one size class.
@@ -500,19 +507,25 @@ __device__ __forceinline__ void hess_all(double2 (&a)[MR][MC], double2 (&y)[MC],
     }
 }
 
+// Terms of the La Budde sum loaded per batch: the ring and beta reads of a
+// batch are all issued before its first multiply-add, so one LDS latency is
+// exposed per batch instead of one per term (the sum keeps its order).
+constexpr int kLbBatch = 2;
+
 // One La Budde step (team-local): row r = rho + 1 of H' is in rowbuf at
 // index rho + k for H'[r][r + k]; sub_in = H'[r + 1][r].  Team lane tl keeps
 // pi_{r,tl} and writes beta_{tl}; under the lane map mp = (d, g, klo, khi) it
 // sums the terms klo..khi of coefficient d; the group's partial sums are added
 // across its lanes and the first lane stores coefficient d.  gmax: the largest
-// group of the team (the same in every lane).
+// group of the team (the same in every lane).  row = (r + d) mod (D + 1), the
+// ring row of the lane's coefficient, kept by the caller (it steps down by one
+// per step, which saves a division per step).
 template <class V>
 __device__ __forceinline__ void labudde_step(int rho, int m, int D, int tl, int4 mp, int gmax,
                                              typename CxT<V>::S m1, typename CxT<V>::S m2, V hrr, V sub_in, V& pik,
                                              const double2* __restrict__ rowbuf, V* __restrict__ betab,
-                                             V* __restrict__ ring) {
+                                             V* __restrict__ ring, int row) {
     const int RS = D + 1;
-    const int r = rho + 1;
     // pi_{r,k} = H'[r+1][r] pi_{r+1,k-1} (lane shift by one), pi_{r,0} = 1
     const V sh = vmk<V>(shr1(pik.x), shr1(pik.y));
     pik = (tl == 0) ? vone<V>() : vmul(sub_in, sh);
@@ -524,8 +537,6 @@ __device__ __forceinline__ void labudde_step(int rho, int m, int D, int tl, int4
     // coefficient d - k - 1 of row r + k + 1, i.e. the same ring row (r + d) % RS,
     // walking down its columns; no slot wraps inside the k loop.
     const int d = mp.x;
-    int row = r % RS + d;
-    if (row >= RS) row -= RS;
     const bool lead = (tl & (mp.y - 1)) == 0;
     V e = vzero<V>();
     if (d >= 0) {
@@ -534,14 +545,21 @@ __device__ __forceinline__ void labudde_step(int rho, int m, int D, int tl, int4
             e = ring[rowp * RS + d];
             if (d >= 1) e = vfms(hrr, ring[row * RS + d - 1], e);
         }
-        const int kend = min(mp.w, min(K, d - 1));
+        const int nt = min(mp.w, min(K, d - 1)) - mp.z + 1;  // terms of this lane (may be <= 0)
         const V* rp = ring + row * RS + d - 1 - mp.z;
         const V* bp = betab + mp.z;
-        for (int k = mp.z; k <= kend; ++k) {
-            e = vfms(bp[0], rp[0], e);
-            ++bp;
-            --rp;
+        int k0 = 0;
+        for (; k0 + kLbBatch <= nt; k0 += kLbBatch) {
+            V bv[kLbBatch], rv[kLbBatch];
+#pragma unroll
+            for (int q = 0; q < kLbBatch; ++q) {
+                bv[q] = bp[k0 + q];
+                rv[q] = rp[-(k0 + q)];
+            }
+#pragma unroll
+            for (int q = 0; q < kLbBatch; ++q) e = vfms(bv[q], rv[q], e);
         }
+        for (; k0 < nt; ++k0) e = vfms(bp[k0], rp[-k0], e);
     }
     // group sums: groups are aligned blocks of 1, 2 or 4 lanes; m1 = 1 in groups
     // of 2 or more, m2 = 1 in groups of 4, else 0 (butterfly over lane ^ 1, ^ 2)
@@ -561,7 +579,7 @@ __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, 
                                              typename CxT<V>::S m1, typename CxT<V>::S m2, int pr, int pc,
                                              bool row_owner_group, double2* __restrict__ rowbuf_own,
                                              const double2* __restrict__ rowbuf, V* __restrict__ betab,
-                                             V* __restrict__ ring, V& pik, V& sub) {
+                                             V* __restrict__ ring, V& pik, V& sub, int& row) {
     if constexpr (I >= 0) {
         for (int p = P - 1; p >= 0; --p) {
             const int rho = p + P * I - O;
@@ -573,11 +591,12 @@ __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, 
             wave_sync();
             const V hrr = vconv<V>(rowbuf[rho]);
             const V sub_next = (rho >= 1) ? vconv<V>(rowbuf[rho - 1]) : vzero<V>();
-            labudde_step<V>(rho, m, D, tl, mp, gmax, m1, m2, hrr, sub, pik, rowbuf, betab, ring);
+            labudde_step<V>(rho, m, D, tl, mp, gmax, m1, m2, hrr, sub, pik, rowbuf, betab, ring, row);
             sub = sub_next;
+            row = (row == 0) ? D : row - 1;  // (r + d) mod (D + 1) for the next r = rho
         }
         labudde_rows<P, Q, MR, MC, I - 1, V, O>(a, m, D, tl, mp, gmax, m1, m2, pr, pc, row_owner_group, rowbuf_own,
-                                                rowbuf, betab, ring, pik, sub);
+                                                rowbuf, betab, ring, pik, sub, row);
     }
 }
 
@@ -625,14 +644,17 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     double2* nb = L.misc + g * 2;
     int* idx = L.idx + g * 64;
 
-    // subsets of this wave (one per group); the mask list or colex unranking
-    // is evaluated on the scalar unit for every group, then selected per lane
+    // subsets of this wave (one per group), on the scalar unit: the mask list,
+    // or the colex unranking of the first rank and the colex successor of each
+    // next one (groups past the end repeat the last subset); selected per lane
     uint64_t mask = 0;
+    {
+        uint64_t mq = masks ? masks[first] : unrank_colex(rank0 + first, n, s, binom);
 #pragma unroll
-    for (int q = 0; q < W; ++q) {
-        const uint64_t gi = (first + q < count) ? first + q : count - 1;
-        const uint64_t mq = masks ? masks[gi] : unrank_colex(rank0 + gi, n, s, binom);
-        if (g == q) mask = mq;
+        for (int q = 0; q < W; ++q) {
+            if (g == q) mask = mq;
+            if (q + 1 < W && first + q + 1 < count) mq = masks ? masks[first + q + 1] : colex_next(mq);
+        }
     }
     for (int e = lane; e < W * 64; e += 64) L.vbuf[e] = cz();
     {
@@ -744,9 +766,12 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         if (tl < RS) ring[((Mp + tl) % RS) * RS + tl] = (tl == 0) ? vone<V>() : vzero<V>();
         V pik = (tl == 0) ? vone<V>() : vzero<V>();
         V sub = vzero<V>();
+        // ring row of the lane's coefficient for the first step (r = m); idle
+        // lanes (d = -1) carry a row they never use
+        int row = (m + max(mp.x, 0)) % RS;
         wave_sync();
         labudde_rows<P, Q, MR, MC, MR - 1, V, O>(a, m, D, tl, mp, gmax, m1, m2, pr, pc, own, rowbuf_own, rowbuf,
-                                                 betab, ring, pik, sub);
+                                                 betab, ring, pik, sub, row);
         // border row: H'[0][k] = y''_{k-1}, H'[0][0] = 0, H'[1][0] = alpha
         if (own && pr == 0) {
 #pragma unroll
@@ -754,7 +779,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         }
         wave_sync();
         const V alpha_t = vconv<V>(L.misc[gt * 2 + 1]);
-        labudde_step<V>(-1, m, D, tl, mp, gmax, m1, m2, vzero<V>(), alpha_t, pik, rowbuf, betab, ring);
+        labudde_step<V>(-1, m, D, tl, mp, gmax, m1, m2, vzero<V>(), alpha_t, pik, rowbuf, betab, ring, row);
         const uint64_t gi = first + gt;
         if (tl <= D && gi < count) {
             V* out = Eout + gi * (uint64_t)(2 * RS);
