@@ -30,9 +30,9 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU (vect
 TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_amd/csrc/charpoly_l88.hip",
                    "paper_2010_15595_amd/csrc/lhaf_kernels.h")
 TRAFFIC = {
-    "sha256": "451e5f4655d2c15f62746ab970eb76a2afe3607ee4ac45f80ee77a01a1e7df10",
+    "sha256": "b13384c3d249a26d304f39be75d96342fa4bff27b8740c21b7f6faa315a47196",
     "kernel": "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>",
-    "fetch_bytes": 826332,      # 403.5 KiB FETCH_SIZE x 2.0
+    "fetch_bytes": 838349,      # 409.4 KiB FETCH_SIZE x 2.0
     "write_bytes": 213955200,   # 208940.6 KiB WRITE_SIZE x 1.0
 }
 
