@@ -440,36 +440,39 @@ __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC
     for (int jj = jj0; jj < Q; ++jj) {
         const int j = Q * KJ + jj;
         if (j > O + m - 3) return;
+        // The lane group holding column j forms the reflector: |x|^2 and the head
+        // x_{j+1} by column sums (the head lives in one lane of the group; the
+        // others add zeros), then v itself, which it writes for everyone.
+        double2 newsub = cz();
         wave_sync();
         if (pc == jj) {
             double part = 0.0;
+            double2 head = cz();
 #pragma unroll
             for (int i = IL; i < MR; ++i) {
                 const int r = pr + P * i;
                 const double2 x = (r >= j + 1) ? a[i][KJ] : cz();
-                vb[r] = x;
                 part += cabs2(x);
+                if (r == j + 1) head = x;
             }
-            part = sum_cols<P>(part);
-            if (pr == 0) nb[0] = make_double2(part, 0.0);
+            const double norm2 = sum_cols<P>(part);
+            const double2 x0 = csum_cols<P>(head);
+            double scale;
+            double2 vhead;
+            householder(norm2, x0, scale, vhead, newsub);
+#pragma unroll
+            for (int i = IL; i < MR; ++i) {
+                const int r = pr + P * i;
+                const double2 x = (r >= j + 1) ? a[i][KJ] : cz();
+                vb[r] = (r == j + 1) ? vhead : cscale(x, scale);
+            }
         }
         wave_sync();
-        const double norm2 = nb[0].x;
-        const double2 x0 = vb[j + 1];
-        double scale;
-        double2 vhead, newsub;
-        householder(norm2, x0, scale, vhead, newsub);
         double2 vr[MR], vc[MC];
 #pragma unroll
-        for (int i = IL; i < MR; ++i) {
-            const int r = pr + P * i;
-            vr[i] = (r == j + 1) ? vhead : cscale(vb[r], scale);
-        }
+        for (int i = IL; i < MR; ++i) vr[i] = vb[pr + P * i];
 #pragma unroll
-        for (int k = KJ; k < MC; ++k) {
-            const int c = pc + Q * k;
-            vc[k] = (c == j + 1) ? vhead : cscale(vb[c], scale);
-        }
+        for (int k = KJ; k < MC; ++k) vc[k] = vb[pc + Q * k];
         // left: H <- (I - v v^H) H
 #pragma unroll
         for (int k = KJ; k < MC; ++k) {
