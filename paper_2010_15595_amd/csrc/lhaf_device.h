@@ -521,13 +521,13 @@ constexpr int kLbBatch = 2;
 // sums the terms klo..khi of coefficient d; the group's partial sums are added
 // across its lanes and the first lane stores coefficient d.  gmax: the largest
 // group of the team (the same in every lane).  row = (r + d) mod (D + 1), the
-// ring row of the lane's coefficient, kept by the caller (it steps down by one
-// per step, which saves a division per step).
+// ring row of the lane's coefficient, and rowoff = row (D + 1), kept by the
+// caller (both step down by one row per step: no division or multiply here).
 template <class V>
 __device__ __forceinline__ void labudde_step(int rho, int m, int D, int tl, int4 mp, int gmax,
                                              typename CxT<V>::S m1, typename CxT<V>::S m2, V hrr, V sub_in, V& pik,
                                              const double2* __restrict__ rowbuf, V* __restrict__ betab,
-                                             V* __restrict__ ring, int row) {
+                                             V* __restrict__ ring, int row, int rowoff) {
     const int RS = D + 1;
     // pi_{r,k} = H'[r+1][r] pi_{r+1,k-1} (lane shift by one), pi_{r,0} = 1
     const V sh = vmk<V>(shr1(pik.x), shr1(pik.y));
@@ -544,12 +544,12 @@ __device__ __forceinline__ void labudde_step(int rho, int m, int D, int tl, int4
     V e = vzero<V>();
     if (d >= 0) {
         if (lead) {
-            const int rowp = (row + 1 == RS) ? 0 : row + 1;
-            e = ring[rowp * RS + d];
-            if (d >= 1) e = vfms(hrr, ring[row * RS + d - 1], e);
+            const int rowpoff = (row + 1 == RS) ? 0 : rowoff + RS;
+            e = ring[rowpoff + d];
+            if (d >= 1) e = vfms(hrr, ring[rowoff + d - 1], e);
         }
         const int nt = min(mp.w, min(K, d - 1)) - mp.z + 1;  // terms of this lane (may be <= 0)
-        const V* rp = ring + row * RS + d - 1 - mp.z;
+        const V* rp = ring + rowoff + d - 1 - mp.z;
         const V* bp = betab + mp.z;
         int k0 = 0;
         for (; k0 + kLbBatch <= nt; k0 += kLbBatch) {
@@ -570,7 +570,7 @@ __device__ __forceinline__ void labudde_step(int rho, int m, int D, int tl, int4
         e = vmk<V>(fma(m1, dpp_mov<0xB1>(e.x), e.x), fma(m1, dpp_mov<0xB1>(e.y), e.y));
         if (gmax > 2) e = vmk<V>(fma(m2, dpp_mov<0x4E>(e.x), e.x), fma(m2, dpp_mov<0x4E>(e.y), e.y));
     }
-    if (lead && d >= 0) ring[row * RS + d] = e;
+    if (lead && d >= 0) ring[rowoff + d] = e;
     wave_sync();
 }
 
@@ -582,7 +582,7 @@ __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, 
                                              typename CxT<V>::S m1, typename CxT<V>::S m2, int pr, int pc,
                                              bool row_owner_group, double2* __restrict__ rowbuf_own,
                                              const double2* __restrict__ rowbuf, V* __restrict__ betab,
-                                             V* __restrict__ ring, V& pik, V& sub, int& row) {
+                                             V* __restrict__ ring, V& pik, V& sub, int& row, int& rowoff) {
     if constexpr (I >= 0) {
         for (int p = P - 1; p >= 0; --p) {
             const int rho = p + P * I - O;
@@ -594,12 +594,14 @@ __device__ __forceinline__ void labudde_rows(const double2 (&a)[MR][MC], int m, 
             wave_sync();
             const V hrr = vconv<V>(rowbuf[rho]);
             const V sub_next = (rho >= 1) ? vconv<V>(rowbuf[rho - 1]) : vzero<V>();
-            labudde_step<V>(rho, m, D, tl, mp, gmax, m1, m2, hrr, sub, pik, rowbuf, betab, ring, row);
+            labudde_step<V>(rho, m, D, tl, mp, gmax, m1, m2, hrr, sub, pik, rowbuf, betab, ring, row, rowoff);
             sub = sub_next;
-            row = (row == 0) ? D : row - 1;  // (r + d) mod (D + 1) for the next r = rho
+            // (r + d) mod (D + 1) for the next r = rho, and its ring offset
+            rowoff = (row == 0) ? D * (D + 1) : rowoff - (D + 1);
+            row = (row == 0) ? D : row - 1;
         }
         labudde_rows<P, Q, MR, MC, I - 1, V, O>(a, m, D, tl, mp, gmax, m1, m2, pr, pc, row_owner_group, rowbuf_own,
-                                                rowbuf, betab, ring, pik, sub, row);
+                                                rowbuf, betab, ring, pik, sub, row, rowoff);
     }
 }
 
@@ -620,7 +622,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
                                               int s, uint64_t rank0, uint64_t count, uint64_t first,
                                               const uint64_t* __restrict__ masks, const uint64_t* __restrict__ binom,
                                               int D, const int4* __restrict__ lbm, V* __restrict__ Eout,
-                                              double2* __restrict__ lds) {
+                                              double2* __restrict__ lds, uint64_t& chain) {
     constexpr int T = TEAM;
     constexpr int G = P * Q;
     constexpr int W = 64 / G;
@@ -648,16 +650,19 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     int* idx = L.idx + g * 64;
 
     // subsets of this wave (one per group), on the scalar unit: the mask list,
-    // or the colex unranking of the first rank and the colex successor of each
-    // next one (groups past the end repeat the last subset); selected per lane
+    // or the colex successor of the previous subset (`chain`: the last subset
+    // of the caller's previous wave over consecutive ranks, 0 for none, when
+    // the first rank is unranked); groups past the end repeat the last subset.
+    // Selected per lane; chain returns this wave's last subset.
     uint64_t mask = 0;
     {
-        uint64_t mq = masks ? masks[first] : unrank_colex(rank0 + first, n, s, binom);
+        uint64_t mq = masks ? masks[first] : (chain ? colex_next(chain) : unrank_colex(rank0 + first, n, s, binom));
 #pragma unroll
         for (int q = 0; q < W; ++q) {
             if (g == q) mask = mq;
             if (q + 1 < W && first + q + 1 < count) mq = masks ? masks[first + q + 1] : colex_next(mq);
         }
+        chain = mq;
     }
     for (int e = lane; e < W * 64; e += 64) L.vbuf[e] = cz();
     {
@@ -772,9 +777,10 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         // ring row of the lane's coefficient for the first step (r = m); idle
         // lanes (d = -1) carry a row they never use
         int row = (m + max(mp.x, 0)) % RS;
+        int rowoff = row * RS;
         wave_sync();
         labudde_rows<P, Q, MR, MC, MR - 1, V, O>(a, m, D, tl, mp, gmax, m1, m2, pr, pc, own, rowbuf_own, rowbuf,
-                                                 betab, ring, pik, sub, row);
+                                                 betab, ring, pik, sub, row, rowoff);
         // border row: H'[0][k] = y''_{k-1}, H'[0][0] = 0, H'[1][0] = alpha
         if (own && pr == 0) {
 #pragma unroll
@@ -782,7 +788,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         }
         wave_sync();
         const V alpha_t = vconv<V>(L.misc[gt * 2 + 1]);
-        labudde_step<V>(-1, m, D, tl, mp, gmax, m1, m2, vzero<V>(), alpha_t, pik, rowbuf, betab, ring, row);
+        labudde_step<V>(-1, m, D, tl, mp, gmax, m1, m2, vzero<V>(), alpha_t, pik, rowbuf, betab, ring, row, rowoff);
         const uint64_t gi = first + gt;
         if (tl <= D && gi < count) {
             V* out = Eout + gi * (uint64_t)(2 * RS);
@@ -801,8 +807,9 @@ __global__ void __launch_bounds__(64)
                     const int4* __restrict__ lbm, V* __restrict__ Eout) {
     extern __shared__ double2 lds[];
     constexpr int W = 64 / (P * Q);
+    uint64_t chain = 0;
     charpoly_wave<P, Q, MR, MC, V, TEAM, O>(A0, dvec, Np, s, rank0, count, (uint64_t)blockIdx.x * W, masks, binom, D,
-                                            lbm, Eout, lds);
+                                            lbm, Eout, lds, chain);
 }
 
 // Persistent form for batches: every wavefront takes tiles from `tiles`
@@ -829,9 +836,10 @@ __global__ void __launch_bounds__(64) charpoly_batch_kernel(const BatchTile* __r
         const int D = it.n + 1;
         if (TEAM < D + 1) continue;  // a team must hold D + 1 coefficients; the plan never sends such tiles
         const int4* lbm = lbmap + lb_table_offset(TEAM, D);
+        uint64_t chain = 0;
         for (uint64_t first = 0; first < tl.count; first += W)
             charpoly_wave<P, Q, MR, MC, V, TEAM, 0, true>(it.A0, it.dvec, it.Np, tl.s, tl.rank0, tl.count, first,
-                                                          nullptr, binom, D, lbm, Ebase + tl.eoff, lds);
+                                                          nullptr, binom, D, lbm, Ebase + tl.eoff, lds, chain);
         wave_sync();
     }
 }

@@ -627,23 +627,24 @@ __global__ void __launch_bounds__(64) small_items_kernel(const int* __restrict__
             const uint64_t cnt = binom[n * kBinomStride + s];
             const double sign = ((n - s) & 1) ? -1.0 : 1.0;
             const int mr = (2 * s + 3) / 4;
+            uint64_t chain = 0;
             for (uint64_t first = 0; first < cnt; first += W) {
                 switch (mr) {
                     case 1:
                         charpoly_wave<4, 4, 1, 1, double2, 16, 0, true>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
-                                                               binom, D, lbm, E, lds);
+                                                               binom, D, lbm, E, lds, chain);
                         break;
                     case 2:
                         charpoly_wave<4, 4, 2, 2, double2, 16, 0, true>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
-                                                               binom, D, lbm, E, lds);
+                                                               binom, D, lbm, E, lds, chain);
                         break;
                     case 3:
                         charpoly_wave<4, 4, 3, 3, double2, 16, 0, true>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
-                                                               binom, D, lbm, E, lds);
+                                                               binom, D, lbm, E, lds, chain);
                         break;
                     default:
                         charpoly_wave<4, 4, 4, 4, double2, 16, 0, true>(it.A0, it.dvec, it.Np, s, first, cnt - first, 0, nullptr,
-                                                               binom, D, lbm, E, lds);
+                                                               binom, D, lbm, E, lds, chain);
                         break;
                 }
                 wave_sync();
