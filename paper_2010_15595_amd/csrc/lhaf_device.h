@@ -276,10 +276,13 @@ __device__ __forceinline__ void rowsum_many(double (&v)[NV]) {
 }
 
 // Right application of a reflector: u_i = sum_k a[i][k] vc[k] for every local
-// row, and the border-row product sum_k y[k] vc[k], reduced together.
-template <int P, int Q, int MR, int MC, int K0>
+// row, and (WY) the border-row product sum_k y[k] vc[k], reduced together.
+// Without WY the border row is a row of the tile (tiles with spare rows in
+// front keep it in the row just above C) and needs nothing extra.
+template <int P, int Q, int MR, int MC, int K0, bool WY = true>
 __device__ __forceinline__ void right_apply(double2 (&a)[MR][MC], double2 (&y)[MC], const double2 (&vc)[MC]) {
-    double v[2 * MR + 2];
+    constexpr int NV = 2 * MR + (WY ? 2 : 0);
+    double v[NV];
 #pragma unroll
     for (int i = 0; i < MR; ++i) {
         double2 u = cz();
@@ -288,23 +291,25 @@ __device__ __forceinline__ void right_apply(double2 (&a)[MR][MC], double2 (&y)[M
         v[2 * i] = u.x;
         v[2 * i + 1] = u.y;
     }
-    {
+    if constexpr (WY) {
         double2 sy = cz();
 #pragma unroll
         for (int k = K0; k < MC; ++k) sy = cfma(y[k], vc[k], sy);
         v[2 * MR] = sy.x;
         v[2 * MR + 1] = sy.y;
     }
-    rowsum_many<P, Q, 2 * MR + 2>(v);
+    rowsum_many<P, Q, NV>(v);
 #pragma unroll
     for (int i = 0; i < MR; ++i) {
         const double2 u = make_double2(v[2 * i], v[2 * i + 1]);
 #pragma unroll
         for (int k = K0; k < MC; ++k) a[i][k] = cfms_cb(u, vc[k], a[i][k]);
     }
-    const double2 sy = make_double2(v[2 * MR], v[2 * MR + 1]);
+    if constexpr (WY) {
+        const double2 sy = make_double2(v[2 * MR], v[2 * MR + 1]);
 #pragma unroll
-    for (int k = K0; k < MC; ++k) y[k] = cfms_cb(sy, vc[k], y[k]);
+        for (int k = K0; k < MC; ++k) y[k] = cfms_cb(sy, vc[k], y[k]);
+    }
 }
 
 template <int P>
@@ -492,7 +497,7 @@ __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC
             }
         }
         // right: H <- H (I - v v^H); border row y^T <- y^T (I - v v^H)
-        right_apply<P, Q, MR, MC, KJ>(a, y, vc);
+        right_apply<P, Q, MR, MC, KJ, (O == 0)>(a, y, vc);
     }
 }
 
@@ -717,6 +722,9 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         const double2 dy = dvec[ok ? idx[c] : 0];
         const double2 dz = dvec[ok ? idx[xc] : 0];
         y[k] = ok ? dy : cz();
+        // with spare rows in front, the border row lives in tile row O - 1
+        if constexpr (O >= 1)
+            if (pr == (O - 1) % P) a[(O - 1) / P][k] = y[k];
         zc[k] = ok ? dz : cz();
     }
 
@@ -745,7 +753,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
 #pragma unroll
             for (int i = 0; i < MR; ++i) a[i][k] = cfms(vr[i], w, a[i][k]);
         }
-        right_apply<P, Q, MR, MC, 0>(a, y, vc);
+        right_apply<P, Q, MR, MC, 0, (O == 0)>(a, y, vc);
     }
     if (lane % G == 0) nb[1] = alpha;
 
@@ -781,10 +789,11 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         wave_sync();
         labudde_rows<P, Q, MR, MC, MR - 1, V, O>(a, m, D, tl, mp, gmax, m1, m2, pr, pc, own, rowbuf_own, rowbuf,
                                                  betab, ring, pik, sub, row, rowoff);
-        // border row: H'[0][k] = y''_{k-1}, H'[0][0] = 0, H'[1][0] = alpha
-        if (own && pr == 0) {
+        // border row: H'[0][k] = y''_{k-1}, H'[0][0] = 0, H'[1][0] = alpha (in y, or
+        // in tile row O - 1 when the tile has spare rows in front)
+        if (own && pr == ((O >= 1) ? (O - 1) % P : 0)) {
 #pragma unroll
-            for (int k = 0; k < MC; ++k) rowbuf_own[pc + Q * k] = y[k];
+            for (int k = 0; k < MC; ++k) rowbuf_own[pc + Q * k] = (O >= 1) ? a[(O - 1) / P][k] : y[k];
         }
         wave_sync();
         const V alpha_t = vconv<V>(L.misc[gt * 2 + 1]);
