@@ -644,15 +644,22 @@ gbs_status gbs_batch_plan_create(const int32_t* dims, int32_t count, gbs_precisi
         hipFree(din);
         return fail(GBS_E_DEVICE, "copy of the tuning batch failed");
     }
+    // Candidates in increasing tile size; the replay time is taken to be
+    // unimodal in it, so the search stops at the first candidate slower than
+    // the best so far.  Only the first candidate gets an untimed warm replay
+    // (code objects and caches are warm for the later ones).
     gbs_plan* best = nullptr;
     float best_ms = 1e30f;
+    bool warm = false;
     for (int64_t ts : {1024, 4096, 16384, 65536}) {
         gbs_plan* p = nullptr;
         st = plan_build(c, dv, prec == GBS_FP32_COMP, ts, round_bytes, &p);
         if (st != GBS_OK) break;
-        // one warm replay, one timed replay
         float ms = 1e30f;
-        st = plan_run(p, din, nullptr, nullptr, p->cs);
+        if (!warm) {
+            st = plan_run(p, din, nullptr, nullptr, p->cs);
+            warm = true;
+        }
         if (st == GBS_OK && hipEventRecord(p->t0, p->cs) != hipSuccess) st = fail(GBS_E_DEVICE, "event record failed");
         if (st == GBS_OK) st = plan_run(p, din, nullptr, nullptr, p->cs);
         if (st == GBS_OK && hipEventRecord(p->t1, p->cs) != hipSuccess) st = fail(GBS_E_DEVICE, "event failed");
@@ -668,6 +675,7 @@ gbs_status gbs_batch_plan_create(const int32_t* dims, int32_t count, gbs_precisi
             best_ms = ms;
         } else {
             plan_free(p);
+            break;
         }
     }
     hipFree(din);
