@@ -22,18 +22,27 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU (vector FMA)
 
-# HBM bytes per launch of the dominant per-subset kernel on the N = 50 step, from
-# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs scaled by the same counters
-# on a plain 256 MiB device copy (fetch x2.0, write x1.0); the command and raw
-# figures are in profiles/charpoly_n50_traffic.md.  Valid only for the kernel
-# sources hashed here: any change to them reports null until re-measured.
-TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_amd/csrc/charpoly_l88.hip",
-                   "paper_2010_15595_amd/csrc/lhaf_kernels.h")
+# HBM bytes per launch (fetched, written) of the largest per-subset kernel
+# instances of the N = 50 step, from rocprofv3 --pmc FETCH_SIZE and --pmc
+# WRITE_SIZE runs scaled by the same counters on a plain 256 MiB device copy
+# (fetch x2.0, write x1.0); the command and raw figures are in
+# profiles/charpoly_n50_traffic.md.  Valid only for the kernel sources hashed
+# here: any change to them reports null until re-measured.
+TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_amd/csrc/lhaf_kernels.h",
+                   "paper_2010_15595_amd/csrc/charpoly_l88.hip", "paper_2010_15595_amd/csrc/charpoly_l84.hip",
+                   "paper_2010_15595_amd/csrc/charpoly_l44.hip")
 TRAFFIC = {
-    "sha256": "b13384c3d249a26d304f39be75d96342fa4bff27b8740c21b7f6faa315a47196",
-    "kernel": "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>",
-    "fetch_bytes": 838349,      # 409.4 KiB FETCH_SIZE x 2.0
-    "write_bytes": 213955200,   # 208940.6 KiB WRITE_SIZE x 1.0
+    "sha256": "41994faa8ad9dd8472d617edb660420dab83814a981caefa857746e3e5ca0020",
+    "kernels": {  # FETCH_SIZE / WRITE_SIZE KiB per dispatch
+        "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1030285, 224652960),  # 503.1 / 219387.7
+        "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>": (823040, 213955200),   # 401.9 / 208940.6
+        "charpoly_kernel<8, 4, 3, 6, double2, 32, 0>": (911917, 224652960),   # 445.3 / 219387.7
+        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1091308, 217246818),  # 532.9 / 212155.1
+        "charpoly_kernel<8, 8, 4, 4, double2, 64, 0>": (821216, 220641300),   # 401.0 / 215470.0
+        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (885106, 213955200),   # 432.2 / 208940.6
+        "charpoly_kernel<8, 8, 5, 5, double2, 64, 6>": (912461, 186896160),   # 445.5 / 182515.8
+        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (830277, 217246818),   # 405.4 / 212155.1
+    },
 }
 
 
@@ -49,9 +58,9 @@ def sources_sha256():
 
 def traffic_entry(kernel):
     """Measured HBM bytes per launch of `kernel`, if they were taken on it and on these sources."""
-    if TRAFFIC is None or TRAFFIC["sha256"] != sources_sha256() or TRAFFIC["kernel"] != kernel:
+    if TRAFFIC is None or TRAFFIC["sha256"] != sources_sha256() or kernel not in TRAFFIC["kernels"]:
         return None
-    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+    return sum(TRAFFIC["kernels"][kernel])
 
 
 def log(*a):
