@@ -32,16 +32,16 @@ TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_
                    "paper_2010_15595_amd/csrc/charpoly_l88.hip", "paper_2010_15595_amd/csrc/charpoly_l84.hip",
                    "paper_2010_15595_amd/csrc/charpoly_l44.hip")
 TRAFFIC = {
-    "sha256": "41994faa8ad9dd8472d617edb660420dab83814a981caefa857746e3e5ca0020",
+    "sha256": "b3222ab69622264c00c8c27bd95a1df03b700b77478a8d03a2265e89ffb410fb",
     "kernels": {  # FETCH_SIZE / WRITE_SIZE KiB per dispatch
-        "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1030285, 224652960),  # 503.1 / 219387.7
-        "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>": (823040, 213955200),   # 401.9 / 208940.6
-        "charpoly_kernel<8, 4, 3, 6, double2, 32, 0>": (911917, 224652960),   # 445.3 / 219387.7
-        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1091308, 217246818),  # 532.9 / 212155.1
-        "charpoly_kernel<8, 8, 4, 4, double2, 64, 0>": (821216, 220641300),   # 401.0 / 215470.0
-        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (885106, 213955200),   # 432.2 / 208940.6
-        "charpoly_kernel<8, 8, 5, 5, double2, 64, 6>": (912461, 186896160),   # 445.5 / 182515.8
-        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (830277, 217246818),   # 405.4 / 212155.1
+        "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>": (1134669, 770238720),  # 554.0 / 752186.2
+        "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1369216, 898611840),  # 668.6 / 877550.6
+        "charpoly_kernel<8, 4, 3, 6, double2, 32, 0>": (1254554, 898611840),  # 612.6 / 877550.6
+        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1227360, 706052160),  # 599.3 / 689504.1
+        "charpoly_kernel<8, 8, 4, 4, double2, 64, 0>": (1100352, 882565200),  # 537.3 / 861880.1
+        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (1179315, 770238720),  # 575.8 / 752186.2
+        "charpoly_kernel<8, 8, 5, 5, double2, 64, 6>": (1013376, 467240400),  # 494.8 / 456289.5
+        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (1102304, 706052160),  # 538.2 / 689504.1
     },
 }
 

@@ -36,7 +36,7 @@ gbs_status fail(gbs_status st, const char* fmt, ...) {
     return st;
 }
 
-constexpr uint64_t kChunk = 1ull << 18;  // subsets per phase-1 launch
+constexpr uint64_t kChunk = gbs::kSubsetsPerLaunch;  // subsets per phase-1 launch
 constexpr int kPerThread = 8;            // subsets per lane in phase 2
 
 uint64_t binom_host(int a, int b) {

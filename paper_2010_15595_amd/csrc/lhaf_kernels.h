@@ -34,6 +34,12 @@ constexpr int kMaxTileM = 56;
 // Largest m on the 8 x 4 grid inside batch plans (its nine- and ten-column
 // persistent instances spill).
 constexpr int kMaxBatchM84 = 32;
+// Subsets per launch of a single evaluation (one size class is split into
+// launches of at most this many).  Larger launches spend less of their time in
+// the partly empty last round of wavefronts and between launches; the
+// coefficient buffer holds 2 (D + 1) complex values per subset (0.9 GB at
+// N = 50, FP64).
+constexpr uint64_t kSubsetsPerLaunch = 1ull << 20;
 
 // Phase 1: one wavefront per pair subset of size s; writes, per subset, the
 // D + 1 leading coefficients of det(xI - C) then of det(xI - C').
