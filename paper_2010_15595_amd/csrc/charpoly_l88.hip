@@ -69,19 +69,21 @@ hipError_t launch_charpoly_l88(const LaunchPhase1& p, hipStream_t st) {
 template <int P, int Q, int MR, int MC, int TEAM>
 static hipError_t launch_charpoly_batch_team(int D_max, int fp32, const BatchTile* tiles, int ntiles,
                                              const BatchItem* items, const uint64_t* binom, const int4* lbmap,
-                                             unsigned* counter, void* Ebase, int grid, hipStream_t st) {
+                                             unsigned* counter, void* Ebase, int max_grid, hipStream_t st) {
     constexpr int W = 64 / (P * Q);
     // every tile of the launch has D <= D_max and the launch's team layout;
     // the LDS size is non-decreasing in D
     const int D = (TEAM < 64) ? std::min(D_max, TEAM - 1) : D_max;
     if (fp32) {
         const size_t lds = charpoly_lds_bytes(W, TEAM, D, sizeof(float2));
-        hipLaunchKernelGGL((charpoly_batch_kernel<P, Q, MR, MC, float2, TEAM>), dim3(grid), dim3(64), lds, st, tiles,
-                           ntiles, items, binom, lbmap, counter, static_cast<float2*>(Ebase));
+        const auto k = charpoly_batch_kernel<P, Q, MR, MC, float2, TEAM>;
+        hipLaunchKernelGGL(k, dim3(persistent_grid(k, lds, max_grid)), dim3(64), lds, st, tiles, ntiles, items, binom,
+                           lbmap, counter, static_cast<float2*>(Ebase));
     } else {
         const size_t lds = charpoly_lds_bytes(W, TEAM, D, sizeof(double2));
-        hipLaunchKernelGGL((charpoly_batch_kernel<P, Q, MR, MC, double2, TEAM>), dim3(grid), dim3(64), lds, st, tiles,
-                           ntiles, items, binom, lbmap, counter, static_cast<double2*>(Ebase));
+        const auto k = charpoly_batch_kernel<P, Q, MR, MC, double2, TEAM>;
+        hipLaunchKernelGGL(k, dim3(persistent_grid(k, lds, max_grid)), dim3(64), lds, st, tiles, ntiles, items, binom,
+                           lbmap, counter, static_cast<double2*>(Ebase));
     }
     return hipGetLastError();
 }
@@ -91,30 +93,30 @@ static hipError_t launch_charpoly_batch_team(int D_max, int fp32, const BatchTil
 template <int P, int Q, int MR, int MC>
 static hipError_t launch_charpoly_batch_t(int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
                                           const BatchItem* items, const uint64_t* binom, const int4* lbmap,
-                                          unsigned* counter, void* Ebase, int grid, hipStream_t st) {
+                                          unsigned* counter, void* Ebase, int max_grid, hipStream_t st) {
     constexpr int G = P * Q;
     if (variant == 0) {
         if constexpr (G < 64)
             return launch_charpoly_batch_team<P, Q, MR, MC, G>(D_max, fp32, tiles, ntiles, items, binom, lbmap, counter,
-                                                               Ebase, grid, st);
+                                                               Ebase, max_grid, st);
         return hipErrorInvalidValue;
     }
     return launch_charpoly_batch_team<P, Q, MR, MC, 64>(D_max, fp32, tiles, ntiles, items, binom, lbmap, counter,
-                                                        Ebase, grid, st);
+                                                        Ebase, max_grid, st);
 }
 
 hipError_t launch_charpoly_batch_l88(int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
                                       const BatchItem* items, const uint64_t* binom, const int4* lbmap, unsigned* counter, void* Ebase,
-                                      int grid, hipStream_t st) {
+                                      int max_grid, hipStream_t st) {
     const int m = 2 * s_rep;
     switch ((m + 7) / 8) {
-        case 1: return launch_charpoly_batch_t<8, 8, 1, 1>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
-        case 2: return launch_charpoly_batch_t<8, 8, 2, 2>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
-        case 3: return launch_charpoly_batch_t<8, 8, 3, 3>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
-        case 4: return launch_charpoly_batch_t<8, 8, 4, 4>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
-        case 5: return launch_charpoly_batch_t<8, 8, 5, 5>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
-        case 6: return launch_charpoly_batch_t<8, 8, 6, 6>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
-        case 7: return launch_charpoly_batch_t<8, 8, 7, 7>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, grid, st);
+        case 1: return launch_charpoly_batch_t<8, 8, 1, 1>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 2: return launch_charpoly_batch_t<8, 8, 2, 2>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 3: return launch_charpoly_batch_t<8, 8, 3, 3>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 4: return launch_charpoly_batch_t<8, 8, 4, 4>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 5: return launch_charpoly_batch_t<8, 8, 5, 5>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 6: return launch_charpoly_batch_t<8, 8, 6, 6>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 7: return launch_charpoly_batch_t<8, 8, 7, 7>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
     }
     return hipErrorInvalidValue;
 }

@@ -32,7 +32,7 @@ namespace {
 
 constexpr int kSeriesPerThread = 8;                   // subsets per lane in the series kernel
 constexpr int kSeriesBlock = 64 * kSeriesPerThread;   // subsets per series block
-constexpr int kPersistentWaves = 256 * 8;             // wavefronts of a persistent launch
+constexpr int kPersistentWaves = 256 * 8;             // wavefronts of the small-item launch
 
 }  // namespace
 
@@ -243,11 +243,11 @@ gbs_status batch_enqueue(DevCtx* c, const BatchSchedule& S, const BatchDev& d, h
             hipStream_t bs = br[b % kBatchBranches];
             HIP_TRY(hipStreamWaitEvent(bs, ev_prep, 0));
             if (r >= 2) HIP_TRY(hipStreamWaitEvent(bs, ev_series[r - 2], 0));
-            const int grid = std::min(L.ntiles, kPersistentWaves);
+            // as many wavefronts as fit on the device, no more than there are tiles
             auto launch = [&]() {
                 return gbs::launch_charpoly_batch(L.layout, L.s_rep, L.variant, S.max_n + 1, S.fp32 ? 1 : 0,
                                                   d.tiles + L.tile_begin, L.ntiles, d.items, d.binom, d.lbmap,
-                                                  d.counters + L.counter, E, grid, bs);
+                                                  d.counters + L.counter, E, L.ntiles, bs);
             };
             if (prof && profiling_on())
                 HIP_TRY(prof_charpoly_launch(L.flops, L.subsets, bs, launch, L.kernel));

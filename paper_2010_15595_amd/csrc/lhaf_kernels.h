@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace gbs {
 
 constexpr int kMaxPairs = 32;       // n = N / 2 <= 32 (N <= 64)
@@ -102,10 +104,25 @@ struct SeriesBlock {
 
 // Persistent per-subset kernel over tiles that all use grid `layout` with the
 // same (MR, MC) as subsets of size s_rep and the same La Budde team variant;
-// D_max sizes the LDS.
+// D_max sizes the LDS.  The launch has as many wavefronts as the device holds
+// at once for that kernel and LDS size (persistent_grid), at most max_grid.
 hipError_t launch_charpoly_batch(int layout, int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles,
                                  int ntiles, const BatchItem* items, const uint64_t* binom, const int4* lbmap,
-                                 unsigned* counter, void* Ebase, int grid, hipStream_t st);
+                                 unsigned* counter, void* Ebase, int max_grid, hipStream_t st);
+
+// Wavefronts (64-thread workgroups) of a persistent launch of `kernel` with
+// `lds` bytes of dynamic LDS: the occupancy limit per CU (registers and LDS)
+// times the CUs of the current device, at most max_grid and at least 1.
+template <class K>
+inline int persistent_grid(K kernel, size_t lds, int max_grid) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, lds) != hipSuccess || per_cu < 1) per_cu = 8;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    const long long g = (long long)per_cu * cus;
+    return (int)std::max<long long>(1, std::min<long long>(g, max_grid));
+}
 // Kernel instance id (layout, MR, MC) of subsets of size s under `layout`.
 int charpoly_instance(int layout, int s);
 // La Budde team variant (0: teams of P Q lanes, 1: one team of 64 lanes) of an
