@@ -241,10 +241,10 @@ typedef struct {
  * class), processes them with persistent per-subset kernels that take tiles
  * largest first from a device counter, then the series kernels and a
  * fixed-order compensated reduction per item; the whole schedule is captured
- * once into a HIP graph.  flags = GBS_PLAN_AUTOTUNE times the lane grid of
- * every n in the batch and candidate tile sizes (1024, 4096, ... in turn, one
- * replay each, until one is slower than the best) on the device and keeps the
- * fastest.  Owns its device workspace (including its own copies of the
+ * once into a HIP graph.  Tiles hold 256 subsets; flags = GBS_PLAN_AUTOTUNE
+ * instead times the lane grid of every n in the batch and candidate tile sizes
+ * (64, 128, 256, 1024, 4096, ... subsets in turn, one replay each, until one
+ * is slower than the best) on the device and keeps the fastest.  Owns its device workspace (including its own copies of the
  * library's binomial and lane-map tables, so it stays valid across
  * gbs_finalize / gbs_init) until gbs_batch_plan_destroy.  GBS_E_TOO_LARGE
  * when an item exceeds GBS_MAX_BATCH_DIM. */

@@ -30,8 +30,7 @@ using namespace gbs_host;
 
 namespace {
 
-constexpr int kSeriesPerThread = 8;                   // subsets per lane in the series kernel
-constexpr int kSeriesBlock = 64 * kSeriesPerThread;   // subsets per series block
+constexpr int kSeriesPerThread = 8;                   // most subsets per lane in the series kernel
 constexpr int kPersistentWaves = 256 * 8;             // wavefronts of the small-item launch
 
 }  // namespace
@@ -60,6 +59,9 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
     S.count = (int)dims.size();
     S.fp32 = fp32;
     S.tile_subsets = tile_subsets;
+    // series blocks stay within one tile: small tiles get fewer subsets per lane
+    S.series_per_thread = (int)std::max<int64_t>(1, std::min<int64_t>(kSeriesPerThread, (tile_subsets + 63) / 64));
+    const int64_t sblock = 64 * (int64_t)S.series_per_thread;
     S.dims = dims;
     const int64_t vbytes = fp32 ? (int64_t)sizeof(float2) : (int64_t)sizeof(double2);
     const int nitems = S.count;
@@ -140,7 +142,7 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
             S.pbeg[i] = pi;
             while (k < ht.size() && ht[k].t.item == i) {
                 tile_pidx[k] = pi;
-                pi += (int64_t)((ht[k].t.count + kSeriesBlock - 1) / kSeriesBlock);
+                pi += (int64_t)((ht[k].t.count + sblock - 1) / sblock);
                 ++k;
             }
         }
@@ -205,7 +207,7 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
         const int n = S.npair[ht[k].t.item];
         auto& v = by[{ht[k].round, n}];
         int64_t pi = tile_pidx[k];
-        for (uint64_t s0 = 0; s0 < ht[k].t.count; s0 += kSeriesBlock)
+        for (uint64_t s0 = 0; s0 < ht[k].t.count; s0 += (uint64_t)sblock)
             v.push_back(gbs::SeriesBlock{pos_of[k], (int)pi++, s0});
     }
     for (auto& kv : by) {
@@ -262,7 +264,7 @@ gbs_status batch_enqueue(DevCtx* c, const BatchSchedule& S, const BatchDev& d, h
         for (; si < S.se.size() && S.se[si].round == r; ++si) {
             const SeriesLaunch& L = S.se[si];
             HIP_TRY(gbs::launch_series_batch(L.n, S.fp32 ? 1 : 0, d.sblocks + L.block_begin, L.nblocks, d.tiles,
-                                             d.items, E, kSeriesPerThread, d.partials, cs));
+                                             d.items, E, S.series_per_thread, d.partials, cs));
         }
         HIP_TRY(new_event(&ev_series[r]));
         HIP_TRY(hipEventRecord(ev_series[r], cs));
@@ -613,7 +615,7 @@ gbs_status gbs_batch_plan_create(const int32_t* dims, int32_t count, gbs_precisi
     if (const char* e = std::getenv("GBS_BATCH_ROUND_MB")) round_bytes = std::max<int64_t>(1, atoll(e)) << 20;
     if (!(flags & GBS_PLAN_AUTOTUNE)) {
         gbs_plan* p = nullptr;
-        st = plan_build(c, dv, prec == GBS_FP32_COMP, 4096, round_bytes, &p);
+        st = plan_build(c, dv, prec == GBS_FP32_COMP, 256, round_bytes, &p);
         if (st != GBS_OK) return st;
         *plan = p;
         return GBS_OK;
@@ -651,7 +653,7 @@ gbs_status gbs_batch_plan_create(const int32_t* dims, int32_t count, gbs_precisi
     gbs_plan* best = nullptr;
     float best_ms = 1e30f;
     bool warm = false;
-    for (int64_t ts : {1024, 4096, 16384, 65536}) {
+    for (int64_t ts : {64, 128, 256, 1024, 4096, 16384, 65536}) {
         gbs_plan* p = nullptr;
         st = plan_build(c, dv, prec == GBS_FP32_COMP, ts, round_bytes, &p);
         if (st != GBS_OK) break;

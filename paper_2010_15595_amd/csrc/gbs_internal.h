@@ -119,6 +119,7 @@ struct BatchSchedule {
     int count = 0;
     bool fp32 = false;
     int64_t tile_subsets = 0;
+    int series_per_thread = 8;  // subsets per lane of a series block (64 lanes; a block never spans tiles)
     int rounds = 0;
     int max_n = 0;
     int64_t subset_terms = 0;

@@ -38,7 +38,7 @@ namespace {
 
 constexpr int kGroup = 8192;                          // samples per lockstep group
 constexpr int64_t kRoundBytes = (int64_t)2 << 30;     // coefficient buffer per round
-constexpr int64_t kTileSubsets = 4096;
+constexpr int64_t kTileSubsets = 256;
 
 // Solves (L L^H) X = Bm in place (L lower, n x n; Bm n x r, row-major).
 void chol_solve(const std::vector<cplx>& L, int n, std::vector<cplx>& Bm, int r) {

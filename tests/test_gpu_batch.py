@@ -106,7 +106,7 @@ def test_batch_autotuned_plan(gbs):
     dims, mats = _items(30, seed=4, lo=10, hi=30)
     plan = gbs.BatchPlan(dims, autotune=True)
     info = plan.info()
-    assert info["tile_subsets"] in (1024, 4096, 16384, 65536)
+    assert info["tile_subsets"] in (64, 128, 256, 1024, 4096, 16384, 65536)
     print(f"[batch autotune] tile {info['tile_subsets']}, {info['tune_ms']:.2f} ms", flush=True)
     got, _ = _run(gbs, plan, mats)
     for i, A in enumerate(mats):
