@@ -26,7 +26,7 @@ static hipError_t launch_charpoly_inst(const LaunchPhase1& p, hipStream_t st) {
 template <int P, int Q, int MR, int MC, int TEAM>
 static hipError_t launch_charpoly_team(const LaunchPhase1& p, hipStream_t st) {
     if constexpr (MC >= 3) {
-        switch (p.no_offset ? 0 : charpoly_front_offset(P, Q, MR, MC, 2 * p.s)) {
+        switch (charpoly_front_offset(P, Q, MR, MC, 2 * p.s)) {
             case 0: return launch_charpoly_inst<P, Q, MR, MC, TEAM, 0>(p, st);
             case 2: return launch_charpoly_inst<P, Q, MR, MC, TEAM, 2>(p, st);
             case 4:
@@ -71,8 +71,8 @@ hipError_t launch_charpoly_l84(const LaunchPhase1& p, hipStream_t st, bool one_t
 }
 
 
-template <int P, int Q, int MR, int MC, int TEAM>
-static hipError_t launch_charpoly_batch_team(int D_max, int fp32, const BatchTile* tiles, int ntiles,
+template <int P, int Q, int MR, int MC, int TEAM, int O>
+static hipError_t launch_charpoly_batch_inst(int D_max, int fp32, const BatchTile* tiles, int ntiles,
                                              const BatchItem* items, const uint64_t* binom, const int4* lbmap,
                                              unsigned* counter, void* Ebase, int max_grid, hipStream_t st) {
     constexpr int W = 64 / (P * Q);
@@ -80,49 +80,81 @@ static hipError_t launch_charpoly_batch_team(int D_max, int fp32, const BatchTil
     // the LDS size is non-decreasing in D
     const int D = (TEAM < 64) ? std::min(D_max, TEAM - 1) : D_max;
     if (fp32) {
-        const size_t lds = charpoly_lds_bytes(W, TEAM, D, sizeof(float2));
-        const auto k = charpoly_batch_kernel<P, Q, MR, MC, float2, TEAM>;
-        hipLaunchKernelGGL(k, dim3(persistent_grid(k, lds, max_grid)), dim3(64), lds, st, tiles, ntiles, items, binom,
-                           lbmap, counter, static_cast<float2*>(Ebase));
+        if constexpr (O == 0) {  // FP32 batches keep C at offset 0
+            const size_t lds = charpoly_lds_bytes(W, TEAM, D, sizeof(float2));
+            const auto k = charpoly_batch_kernel<P, Q, MR, MC, float2, TEAM, 0>;
+            hipLaunchKernelGGL(k, dim3(persistent_grid(k, lds, max_grid)), dim3(64), lds, st, tiles, ntiles, items,
+                               binom, lbmap, counter, static_cast<float2*>(Ebase));
+        } else {
+            return hipErrorInvalidValue;
+        }
     } else {
         const size_t lds = charpoly_lds_bytes(W, TEAM, D, sizeof(double2));
-        const auto k = charpoly_batch_kernel<P, Q, MR, MC, double2, TEAM>;
+        const auto k = charpoly_batch_kernel<P, Q, MR, MC, double2, TEAM, O>;
         hipLaunchKernelGGL(k, dim3(persistent_grid(k, lds, max_grid)), dim3(64), lds, st, tiles, ntiles, items, binom,
                            lbmap, counter, static_cast<double2*>(Ebase));
     }
     return hipGetLastError();
 }
 
+// Tile offset of C (charpoly_front_offset of the launch's m).
+template <int P, int Q, int MR, int MC, int TEAM>
+static hipError_t launch_charpoly_batch_team(int offset, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+                                             const BatchItem* items, const uint64_t* binom, const int4* lbmap,
+                                             unsigned* counter, void* Ebase, int max_grid, hipStream_t st) {
+    switch (offset) {
+        case 0:
+            return launch_charpoly_batch_inst<P, Q, MR, MC, TEAM, 0>(D_max, fp32, tiles, ntiles, items, binom, lbmap,
+                                                                     counter, Ebase, max_grid, st);
+        case 2:
+            if constexpr (charpoly_offset_ok(Q, MC, 2))
+                return launch_charpoly_batch_inst<P, Q, MR, MC, TEAM, 2>(D_max, fp32, tiles, ntiles, items, binom,
+                                                                         lbmap, counter, Ebase, max_grid, st);
+            break;
+        case 4:
+            if constexpr (charpoly_offset_ok(Q, MC, 4))
+                return launch_charpoly_batch_inst<P, Q, MR, MC, TEAM, 4>(D_max, fp32, tiles, ntiles, items, binom,
+                                                                         lbmap, counter, Ebase, max_grid, st);
+            break;
+        case 6:
+            if constexpr (charpoly_offset_ok(Q, MC, 6))
+                return launch_charpoly_batch_inst<P, Q, MR, MC, TEAM, 6>(D_max, fp32, tiles, ntiles, items, binom,
+                                                                         lbmap, counter, Ebase, max_grid, st);
+            break;
+    }
+    return hipErrorInvalidValue;
+}
+
 // Every tile of one launch has team variant `variant` (lb_variant of P Q and
 // its D).
 template <int P, int Q, int MR, int MC>
-static hipError_t launch_charpoly_batch_t(int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
-                                          const BatchItem* items, const uint64_t* binom, const int4* lbmap,
+static hipError_t launch_charpoly_batch_t(int variant, int offset, int D_max, int fp32, const BatchTile* tiles,
+                                          int ntiles, const BatchItem* items, const uint64_t* binom, const int4* lbmap,
                                           unsigned* counter, void* Ebase, int max_grid, hipStream_t st) {
     constexpr int G = P * Q;
     if (variant == 0) {
         if constexpr (G < 64)
-            return launch_charpoly_batch_team<P, Q, MR, MC, G>(D_max, fp32, tiles, ntiles, items, binom, lbmap, counter,
+            return launch_charpoly_batch_team<P, Q, MR, MC, G>(offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter,
                                                                Ebase, max_grid, st);
         return hipErrorInvalidValue;
     }
-    return launch_charpoly_batch_team<P, Q, MR, MC, 64>(D_max, fp32, tiles, ntiles, items, binom, lbmap, counter,
+    return launch_charpoly_batch_team<P, Q, MR, MC, 64>(offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter,
                                                         Ebase, max_grid, st);
 }
 
-hipError_t launch_charpoly_batch_l84(int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+hipError_t launch_charpoly_batch_l84(int s_rep, int variant, int offset, int D_max, int fp32, const BatchTile* tiles, int ntiles,
                                       const BatchItem* items, const uint64_t* binom, const int4* lbmap, unsigned* counter, void* Ebase,
                                       int max_grid, hipStream_t st) {
     const int m = 2 * s_rep;
     switch ((m + 3) / 4) {
-        case 1: return launch_charpoly_batch_t<8, 4, 1, 1>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
-        case 2: return launch_charpoly_batch_t<8, 4, 1, 2>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
-        case 3: return launch_charpoly_batch_t<8, 4, 2, 3>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
-        case 4: return launch_charpoly_batch_t<8, 4, 2, 4>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
-        case 5: return launch_charpoly_batch_t<8, 4, 3, 5>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
-        case 6: return launch_charpoly_batch_t<8, 4, 3, 6>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
-        case 7: return launch_charpoly_batch_t<8, 4, 4, 7>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
-        case 8: return launch_charpoly_batch_t<8, 4, 4, 8>(variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 1: return launch_charpoly_batch_t<8, 4, 1, 1>(variant, offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 2: return launch_charpoly_batch_t<8, 4, 1, 2>(variant, offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 3: return launch_charpoly_batch_t<8, 4, 2, 3>(variant, offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 4: return launch_charpoly_batch_t<8, 4, 2, 4>(variant, offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 5: return launch_charpoly_batch_t<8, 4, 3, 5>(variant, offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 6: return launch_charpoly_batch_t<8, 4, 3, 6>(variant, offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 7: return launch_charpoly_batch_t<8, 4, 4, 7>(variant, offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+        case 8: return launch_charpoly_batch_t<8, 4, 4, 8>(variant, offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
     }
     return hipErrorInvalidValue;
 }

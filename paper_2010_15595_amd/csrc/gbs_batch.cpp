@@ -54,7 +54,7 @@ struct gbs_plan {
 namespace gbs_host {
 
 void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, int64_t tile_subsets,
-                    int64_t round_bytes, BatchSchedule& S) {
+                    int64_t round_bytes, bool tile_offsets, BatchSchedule& S) {
     S = BatchSchedule();
     S.count = (int)dims.size();
     S.fp32 = fp32;
@@ -94,7 +94,7 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
     // tiles: (item, s, rank range); series blocks and partial ranges per item
     struct HostTile {
         gbs::BatchTile t;
-        int inst, layout, variant;
+        int inst, layout, variant, offset;
         double cost;
         int round;
     };
@@ -120,7 +120,10 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
                 h.t.s = s;
                 h.layout = lay;
                 h.variant = gbs::charpoly_variant(lay, n);
-                h.inst = 4 * gbs::charpoly_instance(lay, s) + h.variant;
+                // with tile_offsets, FP64 tiles keep C at the front offset of
+                // their m (a launch per offset); FP32 tiles at offset 0
+                h.offset = (tile_offsets && !fp32) ? layout_front_offset(lay, s) : 0;
+                h.inst = 32 * gbs::charpoly_instance(lay, s) + 8 * h.variant + h.offset;
                 h.cost = subset_flops(n, s) * (double)h.t.count;
                 ht.push_back(h);
             }
@@ -185,7 +188,7 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
                ht[dorder[e]].inst == ht[dorder[q]].inst)
             ++e;
         const HostTile& h = ht[dorder[q]];
-        CharpolyLaunch L{h.round, h.layout, h.t.s, h.inst, h.variant, (int)q, (int)(e - q), (int)S.cp.size()};
+        CharpolyLaunch L{h.round, h.layout, h.t.s, h.inst, h.variant, h.offset, (int)q, (int)(e - q), (int)S.cp.size()};
         for (size_t k = q; k < e; ++k) {
             L.flops += ht[dorder[k]].cost;
             L.subsets += (double)ht[dorder[k]].t.count;
@@ -194,8 +197,8 @@ void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, in
             const int P = (h.layout == gbs::kLayout44) ? 4 : 8, Q = (h.layout == gbs::kLayout88) ? 8 : 4;
             const int m = 2 * h.t.s, team = h.variant ? 64 : P * Q;
             char buf[96];
-            snprintf(buf, sizeof buf, "charpoly_batch_kernel<%d, %d, %d, %d, %s, %d>", P, Q, (m + P - 1) / P,
-                     (m + Q - 1) / Q, fp32 ? "float2" : "double2", team);
+            snprintf(buf, sizeof buf, "charpoly_batch_kernel<%d, %d, %d, %d, %s, %d, %d>", P, Q, (m + P - 1) / P,
+                     (m + Q - 1) / Q, fp32 ? "float2" : "double2", team, h.offset);
             L.kernel = buf;
         }
         S.cp.push_back(L);
@@ -247,7 +250,7 @@ gbs_status batch_enqueue(DevCtx* c, const BatchSchedule& S, const BatchDev& d, h
             if (r >= 2) HIP_TRY(hipStreamWaitEvent(bs, ev_series[r - 2], 0));
             // as many wavefronts as fit on the device, no more than there are tiles
             auto launch = [&]() {
-                return gbs::launch_charpoly_batch(L.layout, L.s_rep, L.variant, S.max_n + 1, S.fp32 ? 1 : 0,
+                return gbs::launch_charpoly_batch(L.layout, L.s_rep, L.variant, L.offset, S.max_n + 1, S.fp32 ? 1 : 0,
                                                   d.tiles + L.tile_begin, L.ntiles, d.items, d.binom, d.lbmap,
                                                   d.counters + L.counter, E, L.ntiles, bs);
             };
@@ -329,7 +332,7 @@ gbs_status plan_build_into(DevCtx* c, const std::vector<int>& dims, bool fp32, i
                            int64_t round_bytes, gbs_plan* p) {
     p->device = c->device;
     BatchSchedule& S = p->S;
-    batch_schedule(c, dims, fp32, tile_subsets, round_bytes, S);
+    batch_schedule(c, dims, fp32, tile_subsets, round_bytes, true, S);
     const int nitems = S.count;
     gbs_status st;
     size_t& B = p->bytes;

@@ -64,7 +64,6 @@ int layout_for(const DevCtx* c, int n, int s, bool batch, bool fp32) {
     return v >= 0 ? v : gbs::charpoly_default_layout(2 * s);
 }
 
-// Tile offset of C in a single-evaluation launch of size-s subsets on `lay`.
 int layout_front_offset(int lay, int s) {
     const int P = (lay == gbs::kLayout44) ? 4 : 8, Q = (lay == gbs::kLayout88) ? 8 : 4, m = 2 * s;
     return gbs::charpoly_front_offset(P, Q, (m + P - 1) / P, (m + Q - 1) / Q, m);
@@ -1100,11 +1099,8 @@ gbs_status autotune_impl(DevCtx* c, int n, gbs_tune_report* rep) {
                 best_lay = lay;
             }
             if (lay == gbs::kLayout84T) continue;
-            // batch tiles keep C at offset 0: time that form for the batch choice
-            if (layout_front_offset(lay, s) != 0) {
-                p1.no_offset = 1;
-                HIP_TRY(time_ns(&ns));
-            }
+            // FP64 batch tiles keep C at the same tile offset: the batch choice
+            // is the fastest grid other than the one-team 8x4 grid
             if (ns < best_multi) {
                 best_multi = ns;
                 best_lay_multi = lay;

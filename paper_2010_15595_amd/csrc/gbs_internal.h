@@ -85,6 +85,8 @@ gbs_status noalloc_setup(DevCtx* c);
 // Lane grid of subsets of size s of an n-pair loop hafnian; batch = true
 // gives the batch-plan choice.
 int layout_for(const DevCtx* c, int n, int s, bool batch = false, bool fp32 = false);
+// Tile offset of C for size-s subsets on `lay` (charpoly_front_offset of m = 2s).
+int layout_front_offset(int lay, int s);
 // Consults the autotune cache / runs the tuner once per n (uses the workspace,
 // so it is called before the caller's matrix is prepared).
 gbs_status maybe_tune(DevCtx* c, int n);
@@ -100,7 +102,7 @@ gbs_status autotune_impl(DevCtx* c, int n, gbs_tune_report* rep);
 
 // One persistent per-subset launch of a batch schedule.
 struct CharpolyLaunch {
-    int round, layout, s_rep, inst, variant;
+    int round, layout, s_rep, inst, variant, offset;
     int tile_begin, ntiles;  // range in the device tile array
     int counter;
     double flops = 0.0, subsets = 0.0;  // yardstick flops and subsets of its tiles
@@ -135,8 +137,11 @@ struct BatchSchedule {
     std::vector<SeriesLaunch> se;
     std::vector<int> small;             // FP64 items with 1 <= n <= kSmallPairs, largest n first: one wavefront each
 };
+// tile_offsets: FP64 tiles keep C at the front tile offset of their m (one
+// persistent launch per offset); captured plans use it, the sampler's eagerly
+// run steps do not (the extra launches cost it more than the offset saves).
 void batch_schedule(const DevCtx* c, const std::vector<int>& dims, bool fp32, int64_t tile_subsets,
-                    int64_t round_bytes, BatchSchedule& S);
+                    int64_t round_bytes, bool tile_offsets, BatchSchedule& S);
 
 // Device arrays a schedule runs on.  `mats` is the packed input.
 struct BatchDev {

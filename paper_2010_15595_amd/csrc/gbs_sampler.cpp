@@ -295,7 +295,7 @@ extern "C" gbs_status gbs_sample_pure(const gbs_z* Q, const gbs_z* alpha, int32_
             for (int n = 1; n <= (*std::max_element(dims.begin(), dims.end()) + 1) / 2; ++n)
                 if ((st = maybe_tune(c, n)) != GBS_OK) return st;
             BatchSchedule S;
-            batch_schedule(c, dims, fp32, kTileSubsets, kRoundBytes, S);
+            batch_schedule(c, dims, fp32, kTileSubsets, kRoundBytes, false, S);
             n_lhaf += S.count;
             n_terms += S.subset_terms;
             for (int N : dims) max_dim = std::max(max_dim, N);

@@ -824,7 +824,8 @@ __global__ void __launch_bounds__(64)
 // Persistent form for batches: every wavefront takes tiles from `tiles`
 // (largest first) through a device counter until none is left, and runs all
 // subsets of each tile.  The counter is cleared by the caller's fill kernel.
-template <int P, int Q, int MR, int MC, class V, int TEAM>
+// All tiles of a launch have C at tile offset O.
+template <int P, int Q, int MR, int MC, class V, int TEAM, int O>
 __global__ void __launch_bounds__(64) charpoly_batch_kernel(const BatchTile* __restrict__ tiles, int ntiles,
                                                             const BatchItem* __restrict__ items,
                                                             const uint64_t* __restrict__ binom,
@@ -847,7 +848,7 @@ __global__ void __launch_bounds__(64) charpoly_batch_kernel(const BatchTile* __r
         const int4* lbm = lbmap + lb_table_offset(TEAM, D);
         uint64_t chain = 0;
         for (uint64_t first = 0; first < tl.count; first += W)
-            charpoly_wave<P, Q, MR, MC, V, TEAM, 0, true>(it.A0, it.dvec, it.Np, tl.s, tl.rank0, tl.count, first,
+            charpoly_wave<P, Q, MR, MC, V, TEAM, O, true>(it.A0, it.dvec, it.Np, tl.s, tl.rank0, tl.count, first,
                                                           nullptr, binom, D, lbm, Ebase + tl.eoff, lds, chain);
         wave_sync();
     }

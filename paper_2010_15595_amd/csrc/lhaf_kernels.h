@@ -19,11 +19,12 @@ constexpr int kBinomStride = 33;    // binomial table C(a, b), 0 <= a, b <= 32
 // The offsets of two tile shapes stay 0 because those instances would spill
 // registers: offset 2 with seven local columns on 8-column grids, and any
 // offset with nine or ten local columns on 4-column grids.
+__host__ __device__ constexpr bool charpoly_offset_ok(int Q, int MC, int o) {
+    return o >= 0 && o < Q && (o == 0 || MC >= 3) && !(Q == 8 && MC == 7 && o == 2) && !(Q == 4 && MC >= 9 && o != 0);
+}
 __host__ __device__ constexpr int charpoly_front_offset(int P, int Q, int MR, int MC, int m) {
     const int o = (MC >= 3) ? ((P * MR < Q * MC ? P * MR : Q * MC) - m) : 0;
-    if (Q == 8 && MC == 7 && o == 2) return 0;
-    if (Q == 4 && MC >= 9) return 0;
-    return o;
+    return charpoly_offset_ok(Q, MC, o) ? o : 0;
 }
 
 // Largest subset matrix (m = 2s) the register-tile kernels take.  An 8 x 8
@@ -58,7 +59,6 @@ struct LaunchPhase1 {
     void* Eout;            // count * 2 * (D + 1) complex (double2, or float2 when fp32)
     int fp32;              // La Budde in complex FP32
     const int4* lbmap;     // La Budde lane maps of every (team width, D) (lb_fill_table)
-    int no_offset = 0;     // 1: C at tile offset 0 (the layout of batch tiles), else charpoly_front_offset
 };
 
 // Phase 2: one lane per subset; signed terms, compensated block partials.
@@ -103,12 +103,14 @@ struct SeriesBlock {
 };
 
 // Persistent per-subset kernel over tiles that all use grid `layout` with the
-// same (MR, MC) as subsets of size s_rep and the same La Budde team variant;
-// D_max sizes the LDS.  The launch has as many wavefronts as the device holds
-// at once for that kernel and LDS size (persistent_grid), at most max_grid.
-hipError_t launch_charpoly_batch(int layout, int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles,
-                                 int ntiles, const BatchItem* items, const uint64_t* binom, const int4* lbmap,
-                                 unsigned* counter, void* Ebase, int max_grid, hipStream_t st);
+// same (MR, MC) as subsets of size s_rep, the same La Budde team variant and C
+// at tile offset `offset` (charpoly_front_offset of their m; 0 on the FP32
+// path); D_max sizes the LDS.  The launch has as many wavefronts as the device
+// holds at once for that kernel and LDS size (persistent_grid), at most
+// max_grid.
+hipError_t launch_charpoly_batch(int layout, int s_rep, int variant, int offset, int D_max, int fp32,
+                                 const BatchTile* tiles, int ntiles, const BatchItem* items, const uint64_t* binom,
+                                 const int4* lbmap, unsigned* counter, void* Ebase, int max_grid, hipStream_t st);
 
 // Wavefronts (64-thread workgroups) of a persistent launch of `kernel` with
 // `lds` bytes of dynamic LDS: the occupancy limit per CU (registers and LDS)

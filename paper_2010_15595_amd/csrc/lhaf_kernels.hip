@@ -437,13 +437,13 @@ bool charpoly_layout_ok(int m, int layout) {
 
 int charpoly_default_layout(int m) { return m <= 16 ? kLayout44 : (m <= 32 ? kLayout84 : kLayout88); }
 
-hipError_t launch_charpoly_batch_l44(int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+hipError_t launch_charpoly_batch_l44(int s_rep, int variant, int offset, int D_max, int fp32, const BatchTile* tiles, int ntiles,
                                      const BatchItem* items, const uint64_t* binom, const int4* lbmap, unsigned* counter, void* Ebase,
                                      int max_grid, hipStream_t st);
-hipError_t launch_charpoly_batch_l84(int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+hipError_t launch_charpoly_batch_l84(int s_rep, int variant, int offset, int D_max, int fp32, const BatchTile* tiles, int ntiles,
                                      const BatchItem* items, const uint64_t* binom, const int4* lbmap, unsigned* counter, void* Ebase,
                                      int max_grid, hipStream_t st);
-hipError_t launch_charpoly_batch_l88(int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles, int ntiles,
+hipError_t launch_charpoly_batch_l88(int s_rep, int variant, int offset, int D_max, int fp32, const BatchTile* tiles, int ntiles,
                                      const BatchItem* items, const uint64_t* binom, const int4* lbmap, unsigned* counter, void* Ebase,
                                      int max_grid, hipStream_t st);
 
@@ -510,19 +510,20 @@ void lb_fill_table(int4* out) {
         }
 }
 
-hipError_t launch_charpoly_batch(int layout, int s_rep, int variant, int D_max, int fp32, const BatchTile* tiles,
-                                 int ntiles, const BatchItem* items, const uint64_t* binom, const int4* lbmap,
-                                 unsigned* counter, void* Ebase, int max_grid, hipStream_t st) {
+hipError_t launch_charpoly_batch(int layout, int s_rep, int variant, int offset, int D_max, int fp32,
+                                 const BatchTile* tiles, int ntiles, const BatchItem* items, const uint64_t* binom,
+                                 const int4* lbmap, unsigned* counter, void* Ebase, int max_grid, hipStream_t st) {
+    if (fp32 && offset != 0) return hipErrorInvalidValue;
     if (!charpoly_layout_ok(2 * s_rep, layout)) return hipErrorInvalidValue;
     if ((layout == kLayout84 || layout == kLayout84T) && 2 * s_rep > kMaxBatchM84) return hipErrorInvalidValue;
     switch (layout) {
         case kLayout44:
-            return launch_charpoly_batch_l44(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+            return launch_charpoly_batch_l44(s_rep, variant, offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
         case kLayout84:
         case kLayout84T:
-            return launch_charpoly_batch_l84(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+            return launch_charpoly_batch_l84(s_rep, variant, offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
         default:
-            return launch_charpoly_batch_l88(s_rep, variant, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
+            return launch_charpoly_batch_l88(s_rep, variant, offset, D_max, fp32, tiles, ntiles, items, binom, lbmap, counter, Ebase, max_grid, st);
     }
 }
 
