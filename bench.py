@@ -32,16 +32,16 @@ TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_
                    "paper_2010_15595_amd/csrc/charpoly_l88.hip", "paper_2010_15595_amd/csrc/charpoly_l84.hip",
                    "paper_2010_15595_amd/csrc/charpoly_l44.hip")
 TRAFFIC = {
-    "sha256": "b3222ab69622264c00c8c27bd95a1df03b700b77478a8d03a2265e89ffb410fb",
+    "sha256": "48757eb23e079276cd194b9ef22e2eeeff5ef515f85996d9cd215d06494ac50c",
     "kernels": {  # FETCH_SIZE / WRITE_SIZE KiB per dispatch
-        "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>": (1134669, 770238720),  # 554.0 / 752186.2
         "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1369216, 898611840),  # 668.6 / 877550.6
-        "charpoly_kernel<8, 4, 3, 6, double2, 32, 0>": (1254554, 898611840),  # 612.6 / 877550.6
-        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1227360, 706052160),  # 599.3 / 689504.1
-        "charpoly_kernel<8, 8, 4, 4, double2, 64, 0>": (1100352, 882565200),  # 537.3 / 861880.1
-        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (1179315, 770238720),  # 575.8 / 752186.2
-        "charpoly_kernel<8, 8, 5, 5, double2, 64, 6>": (1013376, 467240400),  # 494.8 / 456289.5
-        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (1102304, 706052160),  # 538.2 / 689504.1
+        "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>": (1125888, 770238720),  # 549.8 / 752186.2
+        "charpoly_kernel<8, 4, 3, 6, double2, 64, 0>": (1265075, 898611840),  # 617.7 / 877550.6
+        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (1179418, 770238720),  # 575.9 / 752186.2
+        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1251584, 706052160),  # 611.1 / 689504.1
+        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (1117984, 706052160),  # 545.9 / 689504.1
+        "charpoly_kernel<4, 4, 5, 5, double2, 64, 2>": (1384640, 882565200),  # 676.1 / 861880.1
+        "charpoly_kernel<4, 4, 4, 4, double2, 64, 0>": (1117120, 467240400),  # 545.5 / 456289.5
     },
 }
 

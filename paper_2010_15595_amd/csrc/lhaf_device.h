@@ -439,15 +439,15 @@ __host__ __device__ constexpr size_t charpoly_lds_bytes(int W, int T, int D, int
 // local index KJ.
 template <int P, int Q, int MR, int MC, int KJ, int O>
 __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC], int m, int pr, int pc,
-                                           double2* __restrict__ vb, double2* __restrict__ nb) {
+                                           double2* __restrict__ vb) {
     constexpr int IL = (Q * KJ) / P;  // local rows below IL lie above every column of this phase
     constexpr int jj0 = (O > Q * KJ) ? O - Q * KJ : 0;
     for (int jj = jj0; jj < Q; ++jj) {
         const int j = Q * KJ + jj;
         if (j > O + m - 3) return;
-        // The lane group holding column j forms the reflector: |x|^2 and the head
-        // x_{j+1} by column sums (the head lives in one lane of the group; the
-        // others add zeros), then v itself, which it writes for everyone.
+        // The lane group holding column j forms the reflector: |x|^2 by a column
+        // sum, the head x_{j+1} from the one lane of the group that holds it,
+        // then v itself, which it writes for everyone.
         double2 newsub = cz();
         wave_sync();
         if (pc == jj) {
@@ -461,7 +461,14 @@ __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC
                 if (r == j + 1) head = x;
             }
             const double norm2 = sum_cols<P>(part);
-            const double2 x0 = csum_cols<P>(head);
+            // the head is in lane P jj + (j + 1) mod P of the group: with one group
+            // per wavefront it is read from there, cheaper than a column sum of
+            // the others' zeros (with two groups, two reads and a select are not)
+            double2 x0;
+            if constexpr (P * Q == 64)
+                x0 = readlane_c(head, P * jj + (j + 1) % P);
+            else
+                x0 = csum_cols<P>(head);
             double scale;
             double2 vhead;
             householder(norm2, x0, scale, vhead, newsub);
@@ -503,15 +510,15 @@ __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC
 
 template <int P, int Q, int MR, int MC, int KJ, int O>
 __device__ __forceinline__ void hess_all(double2 (&a)[MR][MC], double2 (&y)[MC], int m, int pr, int pc,
-                                         double2* __restrict__ vb, double2* __restrict__ nb) {
+                                         double2* __restrict__ vb) {
     if constexpr (KJ < MC) {
         if constexpr (Q * KJ + Q <= O) {  // the phase lies wholly in the padding
-            hess_all<P, Q, MR, MC, KJ + 1, O>(a, y, m, pr, pc, vb, nb);
+            hess_all<P, Q, MR, MC, KJ + 1, O>(a, y, m, pr, pc, vb);
             return;
         }
         if (Q * KJ > O + m - 3) return;
-        hess_phase<P, Q, MR, MC, KJ, O>(a, y, m, pr, pc, vb, nb);
-        hess_all<P, Q, MR, MC, KJ + 1, O>(a, y, m, pr, pc, vb, nb);
+        hess_phase<P, Q, MR, MC, KJ, O>(a, y, m, pr, pc, vb);
+        hess_all<P, Q, MR, MC, KJ + 1, O>(a, y, m, pr, pc, vb);
     }
 }
 
@@ -758,7 +765,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     if (lane % G == 0) nb[1] = alpha;
 
     // Householder reduction of the C block
-    hess_all<P, Q, MR, MC, 0, O>(a, y, m, pr, pc, vb, nb);
+    hess_all<P, Q, MR, MC, 0, O>(a, y, m, pr, pc, vb);
     // vbuf and idx are dead from here on; the La Budde ring reuses their space
     wave_sync();
 
