@@ -545,18 +545,24 @@ def fig3_sweep(args, gbs):
         torch.cuda.synchronize()
         est = time.perf_counter() - t0
         steps = max(1, min(200, int(1.0 / max(est, 1e-6))))
-        gbs.profile_enable(True)
+        # whole loop hafnians timed without the per-launch profiling events,
+        # then a profiled pass of the same calls for the dominant instance
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         for _ in range(steps):
             gbs.lhaf_device(A_dev, out, ab, stream)
         ev1.record(stream)
         torch.cuda.synchronize()
+        sec = ev0.elapsed_time(ev1) / 1000.0 / steps
+        psteps = max(1, min(steps, 20))
+        gbs.profile_enable(True)
+        for _ in range(psteps):
+            gbs.lhaf_device(A_dev, out, ab, stream)
+        torch.cuda.synchronize()
         prof = gbs.profile_read()
         gbs.profile_enable(False)
-        sec = ev0.elapsed_time(ev1) / 1000.0 / steps
         flops = gbs.yardstick_flops(N)
-        roof = roofline_from_profile(prof, steps, "gather + Householder Hessenberg + La Budde, one size class")
+        roof = roofline_from_profile(prof, psteps, "gather + Householder Hessenberg + La Budde, one size class")
         row = {"fp64_seconds": sec, "fp64_lhaf_per_s": 1.0 / sec, "subset_terms_per_s": float(1 << n) / sec,
                "pct_fp64_peak": 100.0 * flops / sec / (FP64_PEAK_TFLOPS * 1e12),
                "dominant_kernel": roof["kernel"], "dominant_frac": roof["frac"],

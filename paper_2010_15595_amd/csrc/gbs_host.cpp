@@ -37,6 +37,7 @@ gbs_status fail(gbs_status st, const char* fmt, ...) {
 }
 
 constexpr uint64_t kChunk = gbs::kSubsetsPerLaunch;  // subsets per phase-1 launch
+constexpr size_t kConcurrentEBytes = (size_t)1 << 30;  // coefficient bytes of a loop hafnian whose classes run concurrently
 constexpr int kPerThread = 8;            // subsets per lane in phase 2
 
 uint64_t binom_host(int a, int b) {
@@ -165,6 +166,11 @@ gbs_status ctx_init(DevCtx* c) {
     HIP_TRY(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
     HIP_TRY(hipEventCreate(&c->t0));
     HIP_TRY(hipEventCreate(&c->t1));
+    HIP_TRY(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    for (int i = 0; i < kAuxStreams; ++i) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming));
+    }
     std::vector<uint64_t> tab(gbs::kBinomStride * gbs::kBinomStride, 0);
     for (int a = 0; a < gbs::kBinomStride; ++a)
         for (int b = 0; b < gbs::kBinomStride; ++b) tab[a * gbs::kBinomStride + b] = binom_host(a, b);
@@ -211,6 +217,11 @@ void ctx_destroy(DevCtx* c) {
     if (c->done) hipEventDestroy(c->done);
     if (c->t0) hipEventDestroy(c->t0);
     if (c->t1) hipEventDestroy(c->t1);
+    if (c->fork) hipEventDestroy(c->fork);
+    for (int i = 0; i < kAuxStreams; ++i) {
+        if (c->join[i]) hipEventDestroy(c->join[i]);
+        if (c->aux[i]) hipStreamDestroy(c->aux[i]);
+    }
     if (c->stream) hipStreamDestroy(c->stream);
     delete c;
 }
@@ -380,10 +391,13 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
     if (lo_dev) HIP_TRY(gbs::launch_scalar_set(lo_dev, make_double2(0.0, 0.0), nullptr, 0.0, st));
     const bool fp32 = prec == GBS_FP32_COMP;
     const int D = n + 1;
-    uint64_t max_len = 0, total_blocks = 0;
+    uint64_t max_len = 0, total_blocks = 0, total_len = 0;
+    bool one_launch = true;  // every size class in one launch on the register-tile kernels
     const uint64_t per_block = 64ull * kPerThread;
     for (int s = 1; s <= n; ++s) {
         const uint64_t cnt = binom_host(n, s);
+        if (cnt > kChunk || 2 * s > gbs::kMaxTileM) one_launch = false;
+        total_len += cnt;
         for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
             const uint64_t len = std::min(kChunk, cnt - st0);
             max_len = std::max(max_len, len);
@@ -391,11 +405,23 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
         }
     }
     const size_t vbytes = fp32 ? sizeof(float2) : sizeof(double2);
-    gbs_status s1 = ensure_buffer(&c->E, &c->E_cap, (size_t)max_len * 2 * (D + 1) * vbytes, 1);
+    const size_t per_subset = 2 * (size_t)(D + 1) * vbytes;
+    // Small loop hafnians (every class one launch, all coefficient blocks in at
+    // most kConcurrentEBytes): the size classes run concurrently on the
+    // auxiliary streams, each on its own part of E, since one class alone
+    // leaves most of the device idle.  Not while profiling, so that profiled
+    // launches are timed one kernel at a time.  The partial records, and so the
+    // result, are the same as in the one-stream order.
+    const bool concurrent = one_launch && !g_prof && total_len * per_subset <= kConcurrentEBytes;
+    gbs_status s1 = ensure_buffer(&c->E, &c->E_cap, (concurrent ? total_len : max_len) * per_subset, 1);
     if (s1 != GBS_OK) return s1;
     s1 = ensure_buffer((void**)&c->partials, &c->partials_cap, (size_t)total_blocks * 5, sizeof(double));
     if (s1 != GBS_OK) return s1;
-    uint64_t poff = 0;
+    uint64_t poff = 0, eoff = 0;
+    if (concurrent) {
+        HIP_TRY(hipEventRecord(c->fork, st));
+        for (int i = 0; i < kAuxStreams; ++i) HIP_TRY(hipStreamWaitEvent(c->aux[i], c->fork, 0));
+    }
     for (int s = 1; s <= n; ++s) {
         const uint64_t cnt = binom_host(n, s);
         const double sign = ((n - s) & 1) ? -1.0 : 1.0;
@@ -418,15 +444,24 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
                 nl += 2;
                 continue;
             }
-            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, c->E, fp32 ? 1 : 0, c->lbmap};
+            const hipStream_t ls = concurrent ? c->aux[(s - 1) % kAuxStreams] : st;
+            void* Es = concurrent ? static_cast<void*>(static_cast<char*>(c->E) + eoff * per_subset) : c->E;
+            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, Es, fp32 ? 1 : 0, c->lbmap};
             const int lay = layout_for(c, n, s, false, fp32);
             HIP_TRY(timed_launch(
-                kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
-                [&] { return gbs::launch_charpoly(p1, lay, st); }, charpoly_instance_name(lay, s, D, fp32)));
-            gbs::LaunchPhase2 p2{c->E, fp32 ? 1 : 0, len, D, sign, kPerThread, c->partials + 5 * poff, nullptr};
-            HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, st, [&] { return gbs::launch_series(n, p2, st); }));
+                kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, ls,
+                [&] { return gbs::launch_charpoly(p1, lay, ls); }, charpoly_instance_name(lay, s, D, fp32)));
+            gbs::LaunchPhase2 p2{Es, fp32 ? 1 : 0, len, D, sign, kPerThread, c->partials + 5 * poff, nullptr};
+            HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, ls, [&] { return gbs::launch_series(n, p2, ls); }));
             poff += (len + per_block - 1) / per_block;
+            eoff += len;
             nl += 2;
+        }
+    }
+    if (concurrent) {
+        for (int i = 0; i < kAuxStreams; ++i) {
+            HIP_TRY(hipEventRecord(c->join[i], c->aux[i]));
+            HIP_TRY(hipStreamWaitEvent(st, c->join[i], 0));
         }
     }
     HIP_TRY(timed_launch(kProfReduce, 0.0, 0.0, st, [&] {

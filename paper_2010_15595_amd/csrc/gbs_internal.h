@@ -37,10 +37,14 @@ struct BatchRunner;
 
 // Per-device workspace.  All library calls take g_mutex, so one context is
 // used by one call at a time; `done` orders reuse across caller streams.
+constexpr int kAuxStreams = 4;  // streams that run the size classes of a small loop hafnian concurrently
+
 struct DevCtx {
     int device = -1;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr, t0 = nullptr, t1 = nullptr;
+    hipStream_t aux[kAuxStreams] = {};     // default priority, created with the context
+    hipEvent_t fork = nullptr, join[kAuxStreams] = {};
     uint64_t* binom = nullptr;
     int4* lbmap = nullptr;      // La Budde lane maps (gbs::lb_fill_table)
     double2* A0 = nullptr;      // 64 x 64
