@@ -37,7 +37,7 @@ gbs_status fail(gbs_status st, const char* fmt, ...) {
 }
 
 constexpr uint64_t kChunk = gbs::kSubsetsPerLaunch;  // subsets per phase-1 launch
-constexpr size_t kConcurrentEBytes = (size_t)1 << 30;  // coefficient bytes of a loop hafnian whose classes run concurrently
+constexpr size_t kConcurrentEBytes = (size_t)4 << 30;  // coefficient bytes of a loop hafnian whose classes run concurrently
 constexpr int kPerThread = 8;            // subsets per lane in phase 2
 
 uint64_t binom_host(int a, int b) {
