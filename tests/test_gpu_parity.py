@@ -255,6 +255,35 @@ def test_bitwise_determinism_and_device_path(gbs):
     assert float(ab.cpu().numpy()[0]) > abs(v1)
 
 
+@pytest.mark.parametrize("N", [10, 24, 32, 40, 44])
+def test_concurrent_size_classes_match_one_stream(gbs, N):
+    """Loop hafnians with N <= 44 run their size classes concurrently on the
+    context's auxiliary streams; with profiling on they run on one stream.
+    Both orders fill the same partial records, so the results are bitwise
+    equal, and both meet the oracle (long double, N <= 32)."""
+    import torch
+
+    A = workloads.random_normal_symmetric(N, seed=N + 7, scale=0.4)
+    At = torch.from_numpy(A).to("cuda:0")
+    res = []
+    for prof in (False, True):
+        gbs.profile_enable(prof)
+        try:
+            out = torch.zeros(1, dtype=torch.complex128, device="cuda:0")
+            ab = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+            gbs.lhaf_device(At, out, ab)
+            torch.cuda.synchronize()
+            res.append((complex(out.cpu().numpy()[0]), float(ab.cpu().numpy()[0])))
+        finally:
+            gbs.profile_enable(False)
+    gbs.profile_read()
+    assert res[0] == res[1]
+    if N <= 32:
+        ref, absum = oracle.lhaf_pt(A, prec="ld", with_abs=True)
+        ref = oracle.to_complex(ref)
+        assert abs(res[0][0] - ref) <= max(1e-10 * abs(ref), 2e-14 * float(absum))
+
+
 def test_allones_accuracy_report(gbs):
     """Fig. 2 experiment: relative error of lhaf(1_n) vs T(n), printed next to
     the paper's long-double numbers (context), bounded by the normwise gate."""
