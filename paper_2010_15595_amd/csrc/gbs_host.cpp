@@ -422,48 +422,58 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
         HIP_TRY(hipEventRecord(c->fork, st));
         for (int i = 0; i < kAuxStreams; ++i) HIP_TRY(hipStreamWaitEvent(c->aux[i], c->fork, 0));
     }
-    for (int s = 1; s <= n; ++s) {
-        const uint64_t cnt = binom_host(n, s);
-        const double sign = ((n - s) & 1) ? -1.0 : 1.0;
-        for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
-            const uint64_t len = std::min(kChunk, cnt - st0);
-            if (2 * s > gbs::kMaxTileM) {
-                // beyond the register tiles: the LDS-resident FP64 kernel writes the
-                // signed terms, a block reduction folds them into the same partials
+    auto enqueue_classes = [&]() -> gbs_status {
+        for (int s = 1; s <= n; ++s) {
+            const uint64_t cnt = binom_host(n, s);
+            const double sign = ((n - s) & 1) ? -1.0 : 1.0;
+            for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
+                const uint64_t len = std::min(kChunk, cnt - st0);
+                if (2 * s > gbs::kMaxTileM) {
+                    // beyond the register tiles: the LDS-resident FP64 kernel writes the
+                    // signed terms, a block reduction folds them into the same partials
+                    HIP_TRY(timed_launch(
+                        kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
+                        [&] {
+                            return gbs::launch_charpoly_lds(0, gbs::kCharpolyLaBudde, c->A0, c->dvec, Np, s, st0, len,
+                                                            nullptr, c->binom, D, sign, c->E, st);
+                        },
+                        "charpoly_lds_kernel<ArF64, 0>"));
+                    HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, st, [&] {
+                        return gbs::launch_lds_block_reduce(0, c->E, len, kPerThread, c->partials + 5 * poff, nullptr, st);
+                    }));
+                    poff += (len + per_block - 1) / per_block;
+                    nl += 2;
+                    continue;
+                }
+                const hipStream_t ls = concurrent ? c->aux[(s - 1) % kAuxStreams] : st;
+                void* Es = concurrent ? static_cast<void*>(static_cast<char*>(c->E) + eoff * per_subset) : c->E;
+                gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, Es, fp32 ? 1 : 0, c->lbmap};
+                const int lay = layout_for(c, n, s, false, fp32);
                 HIP_TRY(timed_launch(
-                    kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, st,
-                    [&] {
-                        return gbs::launch_charpoly_lds(0, gbs::kCharpolyLaBudde, c->A0, c->dvec, Np, s, st0, len,
-                                                        nullptr, c->binom, D, sign, c->E, st);
-                    },
-                    "charpoly_lds_kernel<ArF64, 0>"));
-                HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, st, [&] {
-                    return gbs::launch_lds_block_reduce(0, c->E, len, kPerThread, c->partials + 5 * poff, nullptr, st);
-                }));
+                    kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, ls,
+                    [&] { return gbs::launch_charpoly(p1, lay, ls); }, charpoly_instance_name(lay, s, D, fp32)));
+                gbs::LaunchPhase2 p2{Es, fp32 ? 1 : 0, len, D, sign, kPerThread, c->partials + 5 * poff, nullptr};
+                HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, ls, [&] { return gbs::launch_series(n, p2, ls); }));
                 poff += (len + per_block - 1) / per_block;
+                eoff += len;
                 nl += 2;
-                continue;
             }
-            const hipStream_t ls = concurrent ? c->aux[(s - 1) % kAuxStreams] : st;
-            void* Es = concurrent ? static_cast<void*>(static_cast<char*>(c->E) + eoff * per_subset) : c->E;
-            gbs::LaunchPhase1 p1{c->A0, c->dvec, Np, s, st0, len, nullptr, c->binom, D, Es, fp32 ? 1 : 0, c->lbmap};
-            const int lay = layout_for(c, n, s, false, fp32);
-            HIP_TRY(timed_launch(
-                kProfCharpoly, subset_flops(n, s) * (double)len, (double)len, ls,
-                [&] { return gbs::launch_charpoly(p1, lay, ls); }, charpoly_instance_name(lay, s, D, fp32)));
-            gbs::LaunchPhase2 p2{Es, fp32 ? 1 : 0, len, D, sign, kPerThread, c->partials + 5 * poff, nullptr};
-            HIP_TRY(timed_launch(kProfSeries, 0.0, (double)len, ls, [&] { return gbs::launch_series(n, p2, ls); }));
-            poff += (len + per_block - 1) / per_block;
-            eoff += len;
-            nl += 2;
         }
-    }
+        return GBS_OK;
+    };
+    const gbs_status enq = enqueue_classes();
     if (concurrent) {
+        // joined back into st even after a failed launch, so that later work on
+        // st is ordered after everything already enqueued on the auxiliary streams
+        hipError_t je = hipSuccess;
         for (int i = 0; i < kAuxStreams; ++i) {
-            HIP_TRY(hipEventRecord(c->join[i], c->aux[i]));
-            HIP_TRY(hipStreamWaitEvent(st, c->join[i], 0));
+            const hipError_t r = hipEventRecord(c->join[i], c->aux[i]);
+            const hipError_t w = (r == hipSuccess) ? hipStreamWaitEvent(st, c->join[i], 0) : r;
+            if (je == hipSuccess) je = w;
         }
+        if (enq == GBS_OK) HIP_TRY(je);
     }
+    if (enq != GBS_OK) return enq;
     HIP_TRY(timed_launch(kProfReduce, 0.0, 0.0, st, [&] {
         return gbs::launch_final_reduce(c->partials, (int64_t)poff, out_dev, abs_dev, st);
     }));
