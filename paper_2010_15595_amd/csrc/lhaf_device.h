@@ -326,14 +326,25 @@ __device__ __forceinline__ double rsq_nr(double x) {
     return y;
 }
 
-// Householder reflector P = I - v v^H (|v|^2 = 2) with P x = -phase |x| e_1:
-// from |x|^2 and the head x0, returns the scale of the tail (v_r = x_r scale),
-// the head of v and the new subdiagonal entry.  |x| = 0 gives v = 0.
+// Householder reflector P = I - v v^H (|v|^2 = 2) with P x = -phase |x| e_1,
+// phase = x0 / |x0| (1 for x0 = 0): from |x|^2 and the head x0, returns the
+// scale of the tail (v_r = x_r scale), the head of v and the new subdiagonal
+// entry.  |x| = 0 gives v = 0.
+// With t = |x| / |x0| = |x|^2 / sqrt(|x0|^2 |x|^2):  |v|^2 / 2 before scaling is
+// |x|^2 + |x0| |x| = |x|^2 + |x0|^2 t,  v_0 = x0 (1 + t) scale  and the new
+// subdiagonal -phase |x| = -x0 t: two reciprocal square roots.  Products
+// |x0|^2 |x|^2 outside the normal range take the three-root form below.
 __device__ __forceinline__ void householder(double norm2, double2 x0, double& scale, double2& vhead,
                                             double2& newsub) {
-    if (norm2 > 0.0) {
+    const double ax2 = cabs2(x0);
+    const double p = ax2 * norm2;
+    if (p >= 0x1p-1022 && p <= 0x1p1022) {
+        const double t = norm2 * rsq_nr(p);
+        scale = rsq_nr(fma(ax2, t, norm2));
+        vhead = cscale(x0, (1.0 + t) * scale);
+        newsub = cscale(x0, -t);
+    } else if (norm2 > 0.0) {
         const double xnorm = norm2 * rsq_nr(norm2);
-        const double ax2 = cabs2(x0);
         double2 phase = make_double2(1.0, 0.0);
         double ax0 = 0.0;
         if (ax2 > 0.0) {
