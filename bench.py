@@ -32,16 +32,18 @@ TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_
                    "paper_2010_15595_amd/csrc/charpoly_l88.hip", "paper_2010_15595_amd/csrc/charpoly_l84.hip",
                    "paper_2010_15595_amd/csrc/charpoly_l44.hip")
 TRAFFIC = {
-    "sha256": "48757eb23e079276cd194b9ef22e2eeeff5ef515f85996d9cd215d06494ac50c",
+    "sha256": "9a85ea190935080d575c4d758ea8bd0e8dcf1be4ac8c1af813417e67cdf34d2e",
     "kernels": {  # FETCH_SIZE / WRITE_SIZE KiB per dispatch
-        "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1369216, 898611840),  # 668.6 / 877550.6
-        "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>": (1125888, 770238720),  # 549.8 / 752186.2
-        "charpoly_kernel<8, 4, 3, 6, double2, 64, 0>": (1265075, 898611840),  # 617.7 / 877550.6
-        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (1179418, 770238720),  # 575.9 / 752186.2
-        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1251584, 706052160),  # 611.1 / 689504.1
-        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (1117984, 706052160),  # 545.9 / 689504.1
-        "charpoly_kernel<4, 4, 5, 5, double2, 64, 2>": (1384640, 882565200),  # 676.1 / 861880.1
-        "charpoly_kernel<4, 4, 4, 4, double2, 64, 0>": (1117120, 467240400),  # 545.5 / 456289.5
+        "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1393229, 898611840),  # 680.3 / 877550.6
+        "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>": (1146394, 770238720),  # 559.8 / 752186.2
+        "charpoly_kernel<8, 4, 3, 6, double2, 64, 0>": (1286502, 898611840),  # 628.2 / 877550.6
+        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (1208781, 770238720),  # 590.2 / 752186.2
+        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1282272, 706052160),  # 626.1 / 689504.1
+        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (1135392, 706052160),  # 554.4 / 689504.1
+        "charpoly_kernel<4, 4, 5, 5, double2, 64, 2>": (1410560, 882565200),  # 688.8 / 861880.1
+        "charpoly_kernel<4, 4, 4, 4, double2, 64, 0>": (1134272, 467240400),  # 553.8 / 456289.5
+        "charpoly_kernel<8, 8, 4, 4, double2, 64, 0>": (1107648, 882565200),  # 540.8 / 861880.1
+        "charpoly_kernel<8, 8, 5, 5, double2, 64, 6>": (1026560, 467240400),  # 501.2 / 456289.5
     },
 }
 
