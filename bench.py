@@ -793,7 +793,11 @@ def main():
             "traffic": traffic_entry(prof["dominant_kernel"]) if args.precision == "fp64" else None,
             "traffic_unit": "HBM bytes per launch of the dominant instance (rocprofv3 FETCH_SIZE and WRITE_SIZE, "
                             "scaled by a plain copy)",
-            "algorithmic_bytes_per_subset": 2 * (n + 2) * 16,
+            # the path's own HBM input and output per loop hafnian: the N x N complex128
+            # matrix in, the complex result and sum |t_S| out (24 B); on top of that the
+            # per-subset kernel hands 2(n + 2) coefficients per subset to the series kernel
+            "algorithmic_bytes_per_lhaf": N * N * 16 + 24,
+            "handoff_bytes_per_subset": 2 * (n + 2) * 16,
             "flops_per_launch": prof["dominant_flops"] / max(1, prof["dominant_launches"]),
             "avg_launch_ms": prof["dominant_ms"] / max(1, prof["dominant_launches"]),
             "launches_per_step": prof["dominant_launches"] / args.steps,
