@@ -41,6 +41,8 @@ extern "C" {
 #define GBS_MAX_BATCH_DIM 56
 /* Size of the fixed per-device scratch array of gbs_lhaf_device_noalloc. */
 #define GBS_NOALLOC_SCRATCH_BYTES (32 << 20)
+/* Largest number of shards of gbs_lhaf_device_shard. */
+#define GBS_MAX_SHARDS 65536
 
 typedef struct { double re, im; } gbs_z;
 
@@ -193,6 +195,29 @@ gbs_status gbs_lhaf_terms(const gbs_z *A, int32_t N, int64_t lda, const uint64_t
  * `stream` (a hipStream_t, NULL = null stream); asynchronous. */
 gbs_status gbs_lhaf_device(const gbs_z *A_dev, int32_t N, gbs_precision prec, gbs_z *out_dev,
                            double *abs_sum_dev, void *stream);
+
+/* One GPU's share of the subset sum, for splitting one loop hafnian over
+ * several GPUs: the power-trace sum is a sum of independent subset terms
+ * (Sec. IV), so shard g of G takes colex ranks [C_s g / G, C_s (g + 1) / G) of
+ * every size class s (C_s = C(n, s), integer division); the G shards cover
+ * every subset once and take the same share of every class.  Writes the
+ * shard's compensated partial sum, five doubles, to partial_dev[0..4] (device
+ * memory): (sum re, compensation re, sum im, compensation im, sum |t_S|).
+ * gbs_combine_partials folds the G records into the loop hafnian.  A, N and
+ * stream as in gbs_lhaf_device (asynchronous, ordered on `stream`); GBS_FP64
+ * or GBS_FP32_COMP (GBS_E_UNSUPPORTED for GBS_DD); 0 <= shard < nshards <=
+ * GBS_MAX_SHARDS (GBS_E_ARG otherwise).  N = 0 puts its single term, 1, in
+ * shard 0.  With nshards = 1 the combined result is bitwise that of
+ * gbs_lhaf_device; with more, it agrees to rounding (the terms are grouped
+ * differently). */
+gbs_status gbs_lhaf_device_shard(const gbs_z *A_dev, int32_t N, gbs_precision prec, int32_t shard,
+                                 int32_t nshards, double *partial_dev, void *stream);
+
+/* Folds `count` partial records of gbs_lhaf_device_shard (host memory, five
+ * doubles each, in shard order) with TwoSum in index order: out = the loop
+ * hafnian, abs_sum (nullable) = sum_S |t_S|.  count >= 1 (GBS_E_ARG
+ * otherwise).  Host only; the same merge as the device reductions. */
+gbs_status gbs_combine_partials(const double *partials, int32_t count, gbs_z *out, double *abs_sum);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

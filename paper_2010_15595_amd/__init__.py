@@ -24,6 +24,8 @@ from ._lib import (  # noqa: F401
     lhaf,
     lhaf_device,
     lhaf_device_noalloc,
+    lhaf_device_shard,
+    combine_partials,
     lhaf_method,
     lhaf_terms,
     lib,

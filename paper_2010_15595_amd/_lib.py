@@ -133,6 +133,11 @@ def lib():
         L.gbs_lhaf_device.restype = st
         L.gbs_lhaf_device_noalloc.argtypes = L.gbs_lhaf_device.argtypes
         L.gbs_lhaf_device_noalloc.restype = st
+        L.gbs_lhaf_device_shard.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+        L.gbs_lhaf_device_shard.restype = st
+        L.gbs_combine_partials.argtypes = [DP, ctypes.c_int32, ZP, DP]
+        L.gbs_combine_partials.restype = st
         L.gbs_selftest.argtypes = [I32P]
         L.gbs_selftest.restype = st
         L.gbs_profile_enable.argtypes = [ctypes.c_int]
@@ -357,6 +362,34 @@ def lhaf_device_noalloc(A, out, abs_sum=None, stream=None, prec=GBS_FP64):
     _check(lib().gbs_lhaf_device_noalloc(ctypes.c_void_p(A.data_ptr()), N, prec, ctypes.c_void_p(out.data_ptr()),
                                          ctypes.c_void_p(abs_sum.data_ptr()) if abs_sum is not None else None,
                                          ctypes.c_void_p(stream.cuda_stream)))
+
+
+def lhaf_device_shard(A, record, shard, nshards, stream=None, prec=GBS_FP64):
+    """Shard ``shard`` of ``nshards`` of the subset sum of a device-resident
+    N x N torch.complex128 matrix: its compensated partial record (five
+    float64 values: sum re, compensation re, sum im, compensation im,
+    sum |t_S|) is written to the device tensor ``record``; stream-ordered."""
+    import torch
+
+    if A.dtype != torch.complex128 or not A.is_cuda or not A.is_contiguous():
+        raise ValueError("A must be a contiguous complex128 device tensor")
+    if record.dtype != torch.float64 or not record.is_cuda or not record.is_contiguous() or record.numel() < 5:
+        raise ValueError("record must be a contiguous float64 device tensor of >= 5 elements")
+    N = A.shape[0]
+    if stream is None:
+        stream = torch.cuda.current_stream(A.device)
+    _check(lib().gbs_lhaf_device_shard(ctypes.c_void_p(A.data_ptr()), N, prec, int(shard), int(nshards),
+                                       ctypes.c_void_p(record.data_ptr()), ctypes.c_void_p(stream.cuda_stream)))
+
+
+def combine_partials(records):
+    """Fold shard records (array of shape (G, 5), in shard order) into
+    (loop hafnian, sum |t_S|)."""
+    r = np.ascontiguousarray(np.asarray(records, dtype=np.float64).reshape(-1, 5))
+    out = gbs_z()
+    ab = ctypes.c_double()
+    _check(lib().gbs_combine_partials(r.ctypes.data_as(DP), r.shape[0], ctypes.byref(out), ctypes.byref(ab)))
+    return complex(out.re, out.im), ab.value
 
 
 def selftest():

@@ -374,13 +374,34 @@ gbs_status run_sum_lds(DevCtx* c, int Np, hipStream_t st, double2* out_dev, doub
     return GBS_OK;
 }
 
+// Colex ranks [lo, hi) of the size-s class taken by shard g of G: the shards
+// split every class evenly, so each takes about 1/G of the work.
+struct RankRange {
+    uint64_t lo, hi;
+};
+RankRange shard_ranks(uint64_t cnt, int g, int G) {
+    return RankRange{cnt * (uint64_t)g / (uint64_t)G, cnt * (uint64_t)(g + 1) / (uint64_t)G};
+}
+
 // lds_method >= 0 selects the LDS-resident kernels with that characteristic-polynomial method.
+// Shard g of G (FP64 / FP32 paths only) sums its ranks of every class; with
+// record_dev set, the compensated partial (sum, compensation re / im, sum |t|)
+// is written there instead of the rounded result.
 gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* abs_dev, int* launches,
-                   gbs_precision prec, double2* lo_dev = nullptr, int lds_method = -1) {
+                   gbs_precision prec, double2* lo_dev = nullptr, int lds_method = -1, int shard = 0,
+                   int nshards = 1, double* record_dev = nullptr) {
     const int n = Np / 2;
     int nl = 0;
-    if (n == 0) {
-        HIP_TRY(gbs::launch_scalar_set(out_dev, make_double2(1.0, 0.0), abs_dev, 1.0, st));
+    if (n == 0) {  // the empty matrix: one term, 1, in shard 0
+        const double one = (shard == 0) ? 1.0 : 0.0;
+        if (record_dev) {
+            HIP_TRY(gbs::launch_scalar_set(reinterpret_cast<double2*>(record_dev), make_double2(one, 0.0),
+                                           record_dev + 4, one, st));
+            HIP_TRY(gbs::launch_scalar_set(reinterpret_cast<double2*>(record_dev + 2), make_double2(0.0, 0.0),
+                                           nullptr, 0.0, st));
+        } else {
+            HIP_TRY(gbs::launch_scalar_set(out_dev, make_double2(one, 0.0), abs_dev, one, st));
+        }
         if (lo_dev) HIP_TRY(gbs::launch_scalar_set(lo_dev, make_double2(0.0, 0.0), nullptr, 0.0, st));
         if (launches) *launches = 1;
         return GBS_OK;
@@ -395,11 +416,11 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
     bool one_launch = true;  // every size class in one launch on the register-tile kernels
     const uint64_t per_block = 64ull * kPerThread;
     for (int s = 1; s <= n; ++s) {
-        const uint64_t cnt = binom_host(n, s);
-        if (cnt > kChunk || 2 * s > gbs::kMaxTileM) one_launch = false;
-        total_len += cnt;
-        for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
-            const uint64_t len = std::min(kChunk, cnt - st0);
+        const RankRange rr = shard_ranks(binom_host(n, s), shard, nshards);
+        if (rr.hi - rr.lo > kChunk || 2 * s > gbs::kMaxTileM) one_launch = false;
+        total_len += rr.hi - rr.lo;
+        for (uint64_t st0 = rr.lo; st0 < rr.hi; st0 += kChunk) {
+            const uint64_t len = std::min(kChunk, rr.hi - st0);
             max_len = std::max(max_len, len);
             total_blocks += (len + per_block - 1) / per_block;
         }
@@ -424,10 +445,10 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
     }
     auto enqueue_classes = [&]() -> gbs_status {
         for (int s = 1; s <= n; ++s) {
-            const uint64_t cnt = binom_host(n, s);
+            const RankRange rr = shard_ranks(binom_host(n, s), shard, nshards);
             const double sign = ((n - s) & 1) ? -1.0 : 1.0;
-            for (uint64_t st0 = 0; st0 < cnt; st0 += kChunk) {
-                const uint64_t len = std::min(kChunk, cnt - st0);
+            for (uint64_t st0 = rr.lo; st0 < rr.hi; st0 += kChunk) {
+                const uint64_t len = std::min(kChunk, rr.hi - st0);
                 if (2 * s > gbs::kMaxTileM) {
                     // beyond the register tiles: the LDS-resident FP64 kernel writes the
                     // signed terms, a block reduction folds them into the same partials
@@ -474,9 +495,15 @@ gbs_status run_sum(DevCtx* c, int Np, hipStream_t st, double2* out_dev, double* 
         if (enq == GBS_OK) HIP_TRY(je);
     }
     if (enq != GBS_OK) return enq;
-    HIP_TRY(timed_launch(kProfReduce, 0.0, 0.0, st, [&] {
-        return gbs::launch_final_reduce(c->partials, (int64_t)poff, out_dev, abs_dev, st);
-    }));
+    if (record_dev) {
+        HIP_TRY(timed_launch(kProfReduce, 0.0, 0.0, st, [&] {
+            return gbs::launch_partials_fold(c->partials, (int64_t)poff, record_dev, st);
+        }));
+    } else {
+        HIP_TRY(timed_launch(kProfReduce, 0.0, 0.0, st, [&] {
+            return gbs::launch_final_reduce(c->partials, (int64_t)poff, out_dev, abs_dev, st);
+        }));
+    }
     if (launches) *launches = nl + 1;
     return GBS_OK;
 }
@@ -957,6 +984,55 @@ gbs_status gbs_lhaf_device(const gbs_z* A_dev, int32_t N, gbs_precision prec, gb
     st = run_sum(c, Np, s, reinterpret_cast<double2*>(out_dev), abs_sum_dev, nullptr, prec);
     if (st != GBS_OK) return st;
     HIP_TRY(hipEventRecord(c->done, s));
+    return GBS_OK;
+}
+
+gbs_status gbs_lhaf_device_shard(const gbs_z* A_dev, int32_t N, gbs_precision prec, int32_t shard, int32_t nshards,
+                                 double* partial_dev, void* stream) {
+    if (N < 0 || (N > 0 && !A_dev) || !partial_dev) return fail(GBS_E_ARG, "bad device arguments");
+    if (nshards < 1 || nshards > GBS_MAX_SHARDS || shard < 0 || shard >= nshards)
+        return fail(GBS_E_ARG, "bad shard %d of %d (1 <= shards <= %d)", shard, nshards, GBS_MAX_SHARDS);
+    if (N > GBS_MAX_DIM) return fail(GBS_E_TOO_LARGE, "dimension %d exceeds %d", N, GBS_MAX_DIM);
+    if (prec == GBS_DD) return fail(GBS_E_UNSUPPORTED, "shards take GBS_FP64 or GBS_FP32_COMP");
+    if (prec != GBS_FP64 && prec != GBS_FP32_COMP) return fail(GBS_E_ARG, "bad precision %d", (int)prec);
+    std::lock_guard<std::mutex> lock(g_mutex);
+    DevCtx* c = nullptr;
+    gbs_status st = current_ctx(&c);
+    if (st != GBS_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int Np = N + (N & 1);
+    st = maybe_tune(c, Np / 2);
+    if (st != GBS_OK) return st;
+    HIP_TRY(hipStreamWaitEvent(s, c->done, 0));
+    if (Np > 0)
+        HIP_TRY(gbs::launch_prep(reinterpret_cast<const double2*>(A_dev), N, N, Np, c->A0, c->dvec, s));
+    st = run_sum(c, Np, s, nullptr, nullptr, nullptr, prec, nullptr, -1, shard, nshards, partial_dev);
+    if (st != GBS_OK) return st;
+    HIP_TRY(hipEventRecord(c->done, s));
+    return GBS_OK;
+}
+
+gbs_status gbs_combine_partials(const double* partials, int32_t count, gbs_z* out, double* abs_sum) {
+    if (count < 1 || !partials || !out) return fail(GBS_E_ARG, "bad partial records");
+    auto two_sum = [](double a, double b, double& e) {
+        const double s = a + b;
+        const double bb = s - a;
+        e = (a - (s - bb)) + (b - bb);
+        return s;
+    };
+    double sr = partials[0], cr = partials[1], si = partials[2], ci = partials[3], ab = partials[4];
+    for (int32_t g = 1; g < count; ++g) {
+        const double* p = partials + 5 * (size_t)g;
+        double e;
+        sr = two_sum(sr, p[0], e);
+        cr = cr + p[1] + e;
+        si = two_sum(si, p[2], e);
+        ci = ci + p[3] + e;
+        ab += p[4];
+    }
+    out->re = sr + cr;
+    out->im = si + ci;
+    if (abs_sum) *abs_sum = ab;
     return GBS_OK;
 }
 

@@ -188,3 +188,32 @@ def test_method_entry_validation():
     B = A.copy()
     B[0, 1] = 1.0
     _expect(-2, gbs.lhaf_method, B, gbs.GBS_CHARPOLY_LABUDDE)
+
+
+def test_combine_partials_keeps_the_compensation():
+    # Folded in shard order with TwoSum: 1e16 + 1 - 1e16 keeps the 1 (a plain
+    # double sum gives 0) and -3 + 2^-60 + 3 keeps the 2^-60.
+    rec = np.array([[1e16, 0.0, -3.0, 0.0, 1e16],
+                    [1.0, 0.0, 2.0 ** -60, 0.0, 1.0],
+                    [-1e16, 0.0, 3.0, 0.0, 1e16]])
+    val, ab = gbs.combine_partials(rec)
+    assert val == complex(1.0, 2.0 ** -60)
+    assert ab == (1e16 + 1.0) + 1e16
+    # the records' own compensations are carried: a single record is sum + compensation
+    val, ab = gbs.combine_partials([[1.0, 2.0 ** -30, 5.0, -2.0 ** -20, 7.0]])
+    assert val == complex(1.0 + 2.0 ** -30, 5.0 - 2.0 ** -20) and ab == 7.0
+    with pytest.raises(gbs.GbsError, match="E_ARG"):
+        gbs.combine_partials(np.zeros((0, 5)))
+
+
+def test_shard_argument_checks_on_the_host():
+    # rejected before any device work, so no GPU is needed
+    L = gbs.lib()
+    A = (ctypes.c_double * 8)()
+    rec = (ctypes.c_double * 5)()
+    for shard, nshards in ((2, 2), (-1, 2), (0, 0), (0, 65537)):
+        assert L.gbs_lhaf_device_shard(A, 2, gbs.GBS_FP64, shard, nshards, rec, None) == -1
+    assert L.gbs_lhaf_device_shard(A, 2, gbs.GBS_FP64, 0, 2, None, None) == -1
+    assert L.gbs_lhaf_device_shard(A, 66, gbs.GBS_FP64, 0, 2, rec, None) == -4
+    assert L.gbs_lhaf_device_shard(A, 2, gbs.GBS_DD, 0, 2, rec, None) == -9
+    assert L.gbs_lhaf_device_shard(A, 2, 7, 0, 2, rec, None) == -1
