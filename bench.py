@@ -587,6 +587,58 @@ def fig3_sweep(args, gbs):
                       "sizes": rows}), flush=True)
 
 
+def shard_split(args, gbs):
+    """One GPU's share of a loop hafnian split over several GPUs: the N matrix
+    of the default line split --shards ways (every shard the same share of
+    every size class), each shard timed alone on the one GPU with HIP events
+    on its stream, the records folded on the host and compared with the
+    whole sum."""
+    import numpy as np
+    import torch
+
+    N, G = args.N, args.shards
+    st = workload(N)
+    A = gbs.expand(st["B"], st["gamma"], st["pattern"])
+    n = (N + 1) // 2
+    torch.cuda.set_device(0)
+    gbs.init(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    A_dev = torch.from_numpy(A).to(dev)
+    if not args.no_autotune:
+        gbs.autotune(n)
+    out = torch.zeros(1, dtype=torch.complex128, device=dev)
+    ab = torch.zeros(1, dtype=torch.float64, device=dev)
+    rec = torch.zeros((G, 5), dtype=torch.float64, device=dev)
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    gbs.lhaf_device(A_dev, out, ab, stream)  # warm-up
+    torch.cuda.synchronize()
+    whole_ms = timed(lambda: gbs.lhaf_device(A_dev, out, ab, stream))
+    shard_ms = [timed(lambda g=g: gbs.lhaf_device_shard(A_dev, rec[g], g, G, stream)) for g in range(G)]
+    val, abs_sum = gbs.combine_partials(rec.cpu().numpy())
+    ref = complex(out.cpu().numpy()[0])
+    diff = abs(val - ref) / float(ab.cpu().numpy()[0])
+    log(f"N={N} in {G} shards: " + " ".join(f"{t:.1f}" for t in shard_ms) + f" ms; whole {whole_ms:.1f} ms; "
+        f"|fold - whole| / sum|t| {diff:.2e}")
+    print(json.dumps({
+        "metric": f"ms per shard of one N={N} loop hafnian split {G} ways (one GPU's share, timed alone)",
+        "value": max(shard_ms), "unit": "ms", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+        "dtype": "c128",
+        "config": {"workload": f"the N={N} matrix of the default line; shard g of {G} takes colex ranks "
+                               f"[C g / {G}, C (g + 1) / {G}) of every size class"},
+        "shard_ms": shard_ms, "whole_ms": whole_ms, "sum_of_shards_over_whole": sum(shard_ms) / whole_ms,
+        "max_over_mean": max(shard_ms) / (sum(shard_ms) / G), "fold_vs_whole_normwise": diff,
+    }), flush=True)
+
+
 def methods_comparison(args, gbs):
     """Sec. IV compares La Budde with diagonalisation: the same subset sum on
     the LDS-resident reference kernels with either method (FP64), beside the
@@ -635,11 +687,13 @@ def main():
                     help="print the hash of the kernel sources the traffic figures are tied to")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["n50", "batch", "sampler", "tvd", "fig2", "fig3", "methods"],
+    ap.add_argument("--workload", choices=["n50", "batch", "sampler", "tvd", "fig2", "fig3", "methods", "shard"],
                     default="n50",
                     help="batch: 4096 loop hafnians of uneven N in [10, 36] from one 100-mode state, "
                          "one captured graph of persistent launches per step; sampler: samples/s of the "
-                         "conditional sampling chain in the Fig. 1 setting; tvd: the Fig. 1 experiment")
+                         "conditional sampling chain in the Fig. 1 setting; tvd: the Fig. 1 experiment; "
+                         "shard: the N loop hafnian split --shards ways, each share timed alone")
+    ap.add_argument("--shards", type=int, default=8, help="shard: number of shares of the subset sum")
     ap.add_argument("--samples", type=int, default=200000, help="sampler / tvd: samples per step / per unitary")
     ap.add_argument("--sampler-modes", type=int, default=6)
     ap.add_argument("--tvd-unitaries", type=int, default=10)
@@ -695,6 +749,8 @@ def main():
         return methods_comparison(args, gbs)
     if args.workload == "fig3":
         return fig3_sweep(args, gbs)
+    if args.workload == "shard":
+        return shard_split(args, gbs)
 
     N = args.N
     st = workload(N)
