@@ -275,7 +275,8 @@ def bench_batch(args, gbs):
         log(f"plain form: {len(mats)} single lhaf_device calls in {pms:.1f} ms = {plain['lhaf_per_s']:.1f} lhaf/s; "
             f"batch speedup {plain['ms'] / (gpu_ms / args.steps):.2f}x; max |diff|/sum|t| {plain['max_normwise_diff_vs_batch']:.2e}")
     # roofline pass: the same schedule issued eagerly (graph replays cannot be
-    # bracketed by events per launch), every persistent launch timed on its stream
+    # bracketed by events per launch) on one stream, every persistent launch
+    # timed alone on the device
     gbs.profile_enable(True)
     for _ in range(args.roofline_steps):
         plan.run(packed, out, ab, stream)
@@ -287,7 +288,7 @@ def bench_batch(args, gbs):
     roof = roofline_from_profile(prof, args.roofline_steps,
                                  "persistent per-subset kernel of one (lane grid, tile) class over the batch's tiles; "
                                  f"average launch from {args.roofline_steps} eager profiled run(s) of the captured "
-                                 "schedule right after the timed graph replays")
+                                 "schedule right after the timed graph replays, one launch at a time")
     roof["traffic"] = None
     log(f"roofline: {roof['kernel']} {roof['achieved']:.2f} TFLOP/s ({100 * roof['frac']:.1f}% of FP64 peak); "
         f"all per-subset launches {roof['all_per_subset_kernels']['achieved']:.2f} TFLOP/s")

@@ -562,7 +562,12 @@ gbs_status plan_run(gbs_plan* p, const gbs_z* mats_dev, gbs_z* out_dev, double* 
         HIP_TRY(hipMemcpyAsync(p->staging, mats_dev, sizeof(double2) * (size_t)p->S.in_elems, hipMemcpyDeviceToDevice,
                                s));
     if (prof && profiling_on()) {
-        // the captured schedule issued eagerly, every per-subset launch timed on its own stream
+        // the captured schedule issued eagerly with every branch on the caller's
+        // stream, so each per-subset launch is timed alone on the whole device (as
+        // single evaluations time theirs), not while it shares the device with
+        // the other branches
+        hipStream_t serial[kBatchBranches];
+        for (hipStream_t& b : serial) b = s;
         size_t next = 0;
         auto new_event = [p, &next](hipEvent_t* e) -> hipError_t {
             if (next == p->eager_events.size()) {
@@ -574,7 +579,7 @@ gbs_status plan_run(gbs_plan* p, const gbs_z* mats_dev, gbs_z* out_dev, double* 
             *e = p->eager_events[next++];
             return hipSuccess;
         };
-        const gbs_status st = batch_enqueue(nullptr, p->S, p->d, s, p->br, new_event, true);
+        const gbs_status st = batch_enqueue(nullptr, p->S, p->d, s, serial, new_event, true);
         if (st != GBS_OK) return st;
     } else {
         HIP_TRY(hipGraphLaunch(p->exec, s));
