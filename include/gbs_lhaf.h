@@ -364,9 +364,10 @@ gbs_status gbs_autotune(int32_t n, gbs_tune_report *report);
 /* Per-kernel timing of the subset-sum kernels, measured with HIP events
  * recorded on the launch stream around every launch while enabled.  While
  * enabled, the launches that otherwise overlap run one at a time: the size
- * classes of a single loop hafnian on the caller's stream, and gbs_batch_run
+ * classes of a single loop hafnian on the caller's stream, gbs_batch_run
  * issues its captured schedule eagerly with every branch on the caller's
- * stream, so each duration is that of the kernel alone on the device. */
+ * stream, and so do the per-step batches of gbs_sample_pure; each duration is
+ * that of the kernel alone on the device. */
 typedef struct {
     double charpoly_ms;        /* summed durations of the per-subset kernels (Hessenberg + La Budde) */
     double series_ms;          /* summed durations of the per-subset series kernels                 */

@@ -547,7 +547,10 @@ gbs_status runner_run(BatchRunner* r, const BatchSchedule& S, const double2* mat
         *e = r->events[r->ev_next++];
         return hipSuccess;
     };
-    return batch_enqueue(r->c, S, d, st, r->br, new_event, true);
+    // while per-launch profiling is on, every branch runs on st (each launch timed alone)
+    hipStream_t serial[kBatchBranches];
+    for (hipStream_t& b : serial) b = st;
+    return batch_enqueue(r->c, S, d, st, profiling_on() ? serial : r->br, new_event, true);
 }
 
 }  // namespace gbs_host
