@@ -32,18 +32,18 @@ TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_
                    "paper_2010_15595_amd/csrc/charpoly_l88.hip", "paper_2010_15595_amd/csrc/charpoly_l84.hip",
                    "paper_2010_15595_amd/csrc/charpoly_l44.hip")
 TRAFFIC = {
-    "sha256": "9a85ea190935080d575c4d758ea8bd0e8dcf1be4ac8c1af813417e67cdf34d2e",
+    "sha256": "caee5e58fbb8de84ac5dcbf355be710e54b7d36a8185e7e7e70a59cbfc931b39",
     "kernels": {  # FETCH_SIZE / WRITE_SIZE KiB per dispatch
-        "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1393229, 898611840),  # 680.3 / 877550.6
-        "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>": (1146394, 770238720),  # 559.8 / 752186.2
-        "charpoly_kernel<8, 4, 3, 6, double2, 64, 0>": (1286502, 898611840),  # 628.2 / 877550.6
-        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (1208781, 770238720),  # 590.2 / 752186.2
-        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1282272, 706052160),  # 626.1 / 689504.1
-        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (1135392, 706052160),  # 554.4 / 689504.1
-        "charpoly_kernel<4, 4, 5, 5, double2, 64, 2>": (1410560, 882565200),  # 688.8 / 861880.1
-        "charpoly_kernel<4, 4, 4, 4, double2, 64, 0>": (1134272, 467240400),  # 553.8 / 456289.5
-        "charpoly_kernel<8, 8, 4, 4, double2, 64, 0>": (1107648, 882565200),  # 540.8 / 861880.1
-        "charpoly_kernel<8, 8, 5, 5, double2, 64, 6>": (1026560, 467240400),  # 501.2 / 456289.5
+        "charpoly_kernel<8, 4, 3, 6, double2, 32, 0>": (1281331, 898611840),  # 625.6 / 877550.6
+        "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1393664, 898611840),  # 680.5 / 877550.6
+        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (1202944, 770238720),  # 587.4 / 752186.2
+        "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>": (1136998, 770238720),  # 555.2 / 752186.2
+        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (1138080, 706052160),  # 555.7 / 689504.1
+        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1291200, 706052160),  # 630.5 / 689504.1
+        "charpoly_kernel<4, 4, 5, 5, double2, 64, 2>": (1397440, 882565200),  # 682.3 / 861880.1
+        "charpoly_kernel<8, 4, 4, 8, double2, 64, 0>": (1314496, 882565200),  # 641.8 / 861880.1
+        "charpoly_kernel<4, 4, 4, 4, double2, 64, 0>": (1131968, 467240400),  # 552.7 / 456289.5
+        "charpoly_kernel<8, 8, 5, 5, double2, 64, 6>": (1038464, 467240400),  # 507.1 / 456289.5
     },
 }
 

@@ -1265,7 +1265,7 @@ gbs_status gbs_selftest(int32_t* failures) {
     DevCtx* c = nullptr;
     gbs_status st = current_ctx(&c);
     if (st != GBS_OK) return st;
-    double hin[64], hout[1152];
+    double hin[64], hout[1408];
     for (int l = 0; l < 64; ++l) hin[l] = std::ldexp(1.0, l % 20) + 0.25 * l;
     double *din = nullptr, *dout = nullptr;
     hipError_t e = dev_malloc((void**)&din, sizeof hin);
@@ -1304,6 +1304,12 @@ gbs_status gbs_selftest(int32_t* failures) {
         const double f4[4] = {1.0, -2.0, 3.0, 0.25};
         for (int j = 0; j < 4; ++j)
             if (std::fabs(hout[896 + 64 * j + l] - f4[j] * s4) > 1e-12 * std::fabs(f4[j] * s4)) ++bad;
+        // sums over the lane quad {4 (l / 4) + q}: row sums of the column-swap 8x4 map
+        double sq = 0.0;
+        for (int q = 0; q < 4; ++q) sq += hin[(l & ~3) + q];
+        const double fq[4] = {1.0, 0.5, -3.0, 2.0};
+        for (int j = 0; j < 4; ++j)
+            if (std::fabs(hout[1152 + 64 * j + l] - fq[j] * sq) > 1e-12 * std::fabs(fq[j] * sq)) ++bad;
     }
     *failures = bad;
     return GBS_OK;

@@ -174,25 +174,111 @@ __device__ __forceinline__ uint64_t colex_next(uint64_t mask) {
 
 // ---------------------------------------------------------------- phase 1
 
-// Lane grids.  A wavefront holds W = 64 / (P Q) subsets of one size class.
-// Lane l = g (P Q) + pc P + pr serves subset group g and owns rows
-// r = pr + P i (i < MR) and columns c = pc + Q k (k < MC) of its subset's matrix.
-
-// Sum over the P consecutive lanes pr = 0..P-1 (P = 4 or 8).
-template <int P>
-__device__ __forceinline__ double sum_cols(double x) {
-    if constexpr (P == 8) x += dpp_mov<0x141>(x);  // row_half_mirror
-    x += dpp_mov<0xB1>(x);                          // quad_perm [1,0,3,2]
-    x += dpp_mov<0x4E>(x);                          // quad_perm [2,3,0,1]
-    return x;
+// Lane grids.  A wavefront holds W = 64 / (P Q) subsets of one size class.  Lane
+// l serves subset group g and owns rows r = pr + P i (i < MR) and columns
+// c = pc + Q k (k < MC) of its subset's matrix; column sums run over the P lanes
+// of one (g, pc), row sums over the Q lanes of one (g, pr).
+//  * Default map: l = g P Q + pc P + pr.  Column sums over P consecutive lanes
+//    (DPP), row sums over stride P (DPP row_ror, permlane swaps).
+//  * Column-swap map (CS, 8 x 4 grid): l = 8 pr + 4 g + pc.  Column sums run
+//    over lane bits 3..5 (row_ror:8 and the two permlane swaps, which reduce
+//    two columns for about the price of one), row sums over lane bits 0..1 (DPP
+//    quad permutations).  It issues fewer instructions and holds fewer
+//    registers; it is used where that lifts an instance to a second wave per
+//    SIMD (the one-team 8 x 4 tiles of 7 and 8 local columns with C at offset
+//    0), since elsewhere its longer chains of dependent swaps cost more than
+//    the instructions it saves.
+template <int P, int Q, bool CS>
+struct LaneMap {
+    __device__ static int pr(int l) { return l % P; }
+    __device__ static int pc(int l) { return (l / P) % Q; }
+    __device__ static int g(int l) { return l / (P * Q); }
+};
+template <>
+struct LaneMap<8, 4, true> {
+    __device__ static int pr(int l) { return l >> 3; }
+    __device__ static int pc(int l) { return l & 3; }
+    __device__ static int g(int l) { return (l >> 2) & 1; }
+};
+template <int P, int Q, int MR, int MC, int TEAM, int O>
+constexpr bool lane_map_cs() {
+    return P == 8 && Q == 4 && TEAM == 64 && MR == 4 && MC >= 7 && O == 0;
 }
 
-// Sum over the Q lanes pc = 0..Q-1 (stride P) of one group.  Each level adds
-// two values that the partner lane adds in the other order, so all Q lanes end
-// with the same bits.
-template <int P, int Q>
+// Sums of NV values over the 8 lanes {l mod 8 + 8 q : q = 0..7}, all at once.
+// The swap levels (lane ^ 32, then lane ^ 16) move values in pairs: each leaves
+// every lane with half of the values summed over its partner (reduce-scatter);
+// the lane ^ 8 level is a DPP butterfly; the same swaps run backwards to hand
+// every lane all NV totals (all-gather).  Each total is formed in one place
+// and copied, so all 8 lanes end with the same bits.
+template <int NV>
+__device__ __forceinline__ void stride8_sum_many(double (&v)[NV]) {
+    static_assert(NV % 2 == 0, "even number of values");
+    constexpr int NA = NV / 2, NB = (NA + 1) / 2;
+    double a[NA], b[NB];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+        double x = v[2 * j], y = v[2 * j + 1];
+        swap32(x, y);
+        a[j] = x + y;  // lanes 0..31: total of v[2j]; lanes 32..63: of v[2j+1]
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        double x = a[2 * j], y = (2 * j + 1 < NA) ? a[2 * j + 1] : 0.0;
+        swap16(x, y);
+        b[j] = x + y;  // even rows: a[2j], odd rows: a[2j+1]
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) b[j] += dpp_mov<0x128>(b[j]);  // row_ror:8 (lane ^ 8)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        double x = b[j], y = b[j];
+        swap16(x, y);
+        a[2 * j] = x;
+        if (2 * j + 1 < NA) a[2 * j + 1] = y;
+    }
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+        double x = a[j], y = a[j];
+        swap32(x, y);
+        v[2 * j] = x;
+        v[2 * j + 1] = y;
+    }
+}
+
+// Sum over the P lanes of one column group.  Each level adds two values that
+// the partner lane adds in the other order, so all P lanes end with the same
+// bits.
+template <int P, bool CS>
+__device__ __forceinline__ double sum_cols(double x) {
+    if constexpr (CS) {
+        return sum_stride8(x);
+    } else {
+        if constexpr (P == 8) x += dpp_mov<0x141>(x);  // row_half_mirror
+        x += dpp_mov<0xB1>(x);                          // quad_perm [1,0,3,2]
+        x += dpp_mov<0x4E>(x);                          // quad_perm [2,3,0,1]
+        return x;
+    }
+}
+
+// Column sums of NV values at once.
+template <int P, bool CS, int NV>
+__device__ __forceinline__ void colsum_many(double (&v)[NV]) {
+    if constexpr (CS) {
+        stride8_sum_many<NV>(v);
+    } else {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = sum_cols<P, false>(v[j]);
+    }
+}
+
+// Sum over the Q lanes of one row group (same bits in all Q lanes).
+template <int P, int Q, bool CS>
 __device__ __forceinline__ double sum_rows(double x) {
-    if constexpr (P == 8 && Q == 8) {
+    if constexpr (CS) {
+        x += dpp_mov<0xB1>(x);   // quad_perm [1,0,3,2] (lane ^ 1)
+        x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1] (lane ^ 2)
+    } else if constexpr (P == 8 && Q == 8) {
         x += dpp_mov<0x128>(x);  // row_ror:8 (lane ^ 8)
         x = swap_sum16(x);       // lane ^ 16
         x = swap_sum32(x);       // lane ^ 32
@@ -217,41 +303,12 @@ __device__ __forceinline__ double sum_rows(double x) {
 // in-row level is a DPP butterfly, and the same swaps run backwards to hand
 // every lane all NV totals (all-gather).  Each total is formed in one place
 // and copied, so all Q lanes end with the same bits.
-template <int P, int Q, int NV>
+template <int P, int Q, bool CS, int NV>
 __device__ __forceinline__ void rowsum_many(double (&v)[NV]) {
     static_assert(NV % 2 == 0, "even number of values");
-    if constexpr (P == 8 && Q == 8) {
-        constexpr int NA = NV / 2, NB = (NA + 1) / 2;
-        double a[NA], b[NB];
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-            double x = v[2 * j], y = v[2 * j + 1];
-            swap32(x, y);
-            a[j] = x + y;  // lanes 0..31: total of v[2j]; lanes 32..63: of v[2j+1]
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            double x = a[2 * j], y = (2 * j + 1 < NA) ? a[2 * j + 1] : 0.0;
-            swap16(x, y);
-            b[j] = x + y;  // even rows: a[2j], odd rows: a[2j+1]
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) b[j] += dpp_mov<0x128>(b[j]);  // row_ror:8 (lane ^ 8)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            double x = b[j], y = b[j];
-            swap16(x, y);
-            a[2 * j] = x;
-            if (2 * j + 1 < NA) a[2 * j + 1] = y;
-        }
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-            double x = a[j], y = a[j];
-            swap32(x, y);
-            v[2 * j] = x;
-            v[2 * j + 1] = y;
-        }
-    } else if constexpr (P == 8 && Q == 4) {
+    if constexpr (!CS && P == 8 && Q == 8) {
+        stride8_sum_many<NV>(v);
+    } else if constexpr (!CS && P == 8 && Q == 4) {
         constexpr int NB = NV / 2;
         double b[NB];
 #pragma unroll
@@ -271,7 +328,34 @@ __device__ __forceinline__ void rowsum_many(double (&v)[NV]) {
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < NV; ++j) v[j] = sum_rows<P, Q>(v[j]);
+        for (int j = 0; j < NV; ++j) v[j] = sum_rows<P, Q, CS>(v[j]);
+    }
+}
+
+// Left application of a reflector to local columns K .. MC-1 over local rows
+// I0 .. MR-1: w_k = sum_i conj(v_i) a[i][k] (a column sum), a[i][k] -= v_i w_k.
+// With the column-swap map two columns are reduced together.
+template <int P, bool CS, int MR, int MC, int I0, int K>
+__device__ __forceinline__ void left_apply(double2 (&a)[MR][MC], const double2 (&vr)[MR]) {
+    if constexpr (K < MC) {
+        constexpr int NK = (CS && K + 1 < MC) ? 2 : 1;
+        double v[2 * NK];
+#pragma unroll
+        for (int q = 0; q < NK; ++q) {
+            double2 w = cz();
+#pragma unroll
+            for (int i = I0; i < MR; ++i) w = cfma_ca(vr[i], a[i][K + q], w);
+            v[2 * q] = w.x;
+            v[2 * q + 1] = w.y;
+        }
+        colsum_many<P, CS, 2 * NK>(v);
+#pragma unroll
+        for (int q = 0; q < NK; ++q) {
+            const double2 w = make_double2(v[2 * q], v[2 * q + 1]);
+#pragma unroll
+            for (int i = I0; i < MR; ++i) a[i][K + q] = cfms(vr[i], w, a[i][K + q]);
+        }
+        left_apply<P, CS, MR, MC, I0, K + NK>(a, vr);
     }
 }
 
@@ -279,7 +363,7 @@ __device__ __forceinline__ void rowsum_many(double (&v)[NV]) {
 // row, and (WY) the border-row product sum_k y[k] vc[k], reduced together.
 // Without WY the border row is a row of the tile (tiles with spare rows in
 // front keep it in the row just above C) and needs nothing extra.
-template <int P, int Q, int MR, int MC, int K0, bool WY = true>
+template <int P, int Q, bool CS, int MR, int MC, int K0, bool WY = true>
 __device__ __forceinline__ void right_apply(double2 (&a)[MR][MC], double2 (&y)[MC], const double2 (&vc)[MC]) {
     constexpr int NV = 2 * MR + (WY ? 2 : 0);
     double v[NV];
@@ -298,7 +382,7 @@ __device__ __forceinline__ void right_apply(double2 (&a)[MR][MC], double2 (&y)[M
         v[2 * MR] = sy.x;
         v[2 * MR + 1] = sy.y;
     }
-    rowsum_many<P, Q, NV>(v);
+    rowsum_many<P, Q, CS, NV>(v);
 #pragma unroll
     for (int i = 0; i < MR; ++i) {
         const double2 u = make_double2(v[2 * i], v[2 * i + 1]);
@@ -312,10 +396,10 @@ __device__ __forceinline__ void right_apply(double2 (&a)[MR][MC], double2 (&y)[M
     }
 }
 
-template <int P>
-__device__ __forceinline__ double2 csum_cols(double2 a) { return make_double2(sum_cols<P>(a.x), sum_cols<P>(a.y)); }
-template <int P, int Q>
-__device__ __forceinline__ double2 csum_rows(double2 a) { return make_double2(sum_rows<P, Q>(a.x), sum_rows<P, Q>(a.y)); }
+template <int P, bool CS>
+__device__ __forceinline__ double2 csum_cols(double2 a) {
+    return make_double2(sum_cols<P, CS>(a.x), sum_cols<P, CS>(a.y));
+}
 
 // 1/sqrt(x), x > 0: hardware estimate and two Newton steps (full FP64 accuracy).
 __device__ __forceinline__ double rsq_nr(double x) {
@@ -448,7 +532,7 @@ __host__ __device__ constexpr size_t charpoly_lds_bytes(int W, int T, int D, int
 // (indices below O are zero padding): reflector j (a tile index) zeroes
 // column j below row j + 1, for j = O .. O+m-3; phase KJ takes the columns of
 // local index KJ.
-template <int P, int Q, int MR, int MC, int KJ, int O>
+template <int P, int Q, bool CS, int MR, int MC, int KJ, int O>
 __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC], int m, int pr, int pc,
                                            double2* __restrict__ vb) {
     constexpr int IL = (Q * KJ) / P;  // local rows below IL lie above every column of this phase
@@ -458,10 +542,15 @@ __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC
         if (j > O + m - 3) return;
         // The lane group holding column j forms the reflector: |x|^2 by a column
         // sum, the head x_{j+1} from the one lane of the group that holds it,
-        // then v itself, which it writes for everyone.
+        // then v itself, which it writes for everyone.  With the column-swap map
+        // every lane takes the column sums (on its own local column KJ, |x|^2 and
+        // the head together) before the group's branch, so the swaps run on the
+        // whole wavefront.
         double2 newsub = cz();
+        double norm2 = 0.0;
+        double2 x0 = cz();
         wave_sync();
-        if (pc == jj) {
+        if constexpr (CS) {
             double part = 0.0;
             double2 head = cz();
 #pragma unroll
@@ -471,15 +560,32 @@ __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC
                 part += cabs2(x);
                 if (r == j + 1) head = x;
             }
-            const double norm2 = sum_cols<P>(part);
-            // the head is in lane P jj + (j + 1) mod P of the group: with one group
-            // per wavefront it is read from there, cheaper than a column sum of
-            // the others' zeros (with two groups, two reads and a select are not)
-            double2 x0;
-            if constexpr (P * Q == 64)
-                x0 = readlane_c(head, P * jj + (j + 1) % P);
-            else
-                x0 = csum_cols<P>(head);
+            double sv[4] = {part, head.x, head.y, 0.0};
+            colsum_many<P, CS, 4>(sv);
+            norm2 = sv[0];
+            x0 = make_double2(sv[1], sv[2]);
+        }
+        if (pc == jj) {
+            if constexpr (!CS) {
+                double part = 0.0;
+                double2 head = cz();
+#pragma unroll
+                for (int i = IL; i < MR; ++i) {
+                    const int r = pr + P * i;
+                    const double2 x = (r >= j + 1) ? a[i][KJ] : cz();
+                    part += cabs2(x);
+                    if (r == j + 1) head = x;
+                }
+                norm2 = sum_cols<P, CS>(part);
+                // the head is in lane P jj + (j + 1) mod P of the group: with one
+                // group per wavefront it is read from there, cheaper than a column
+                // sum of the others' zeros (with two groups, two reads and a
+                // select are not)
+                if constexpr (P * Q == 64)
+                    x0 = readlane_c(head, P * jj + (j + 1) % P);
+                else
+                    x0 = csum_cols<P, CS>(head);
+            }
             double scale;
             double2 vhead;
             householder(norm2, x0, scale, vhead, newsub);
@@ -497,15 +603,7 @@ __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC
 #pragma unroll
         for (int k = KJ; k < MC; ++k) vc[k] = vb[pc + Q * k];
         // left: H <- (I - v v^H) H
-#pragma unroll
-        for (int k = KJ; k < MC; ++k) {
-            double2 w = cz();
-#pragma unroll
-            for (int i = IL; i < MR; ++i) w = cfma_ca(vr[i], a[i][k], w);
-            w = csum_cols<P>(w);
-#pragma unroll
-            for (int i = IL; i < MR; ++i) a[i][k] = cfms(vr[i], w, a[i][k]);
-        }
+        left_apply<P, CS, MR, MC, IL, KJ>(a, vr);
         if (pc == jj) {
 #pragma unroll
             for (int i = IL; i < MR; ++i) {
@@ -515,21 +613,21 @@ __device__ __forceinline__ void hess_phase(double2 (&a)[MR][MC], double2 (&y)[MC
             }
         }
         // right: H <- H (I - v v^H); border row y^T <- y^T (I - v v^H)
-        right_apply<P, Q, MR, MC, KJ, (O == 0)>(a, y, vc);
+        right_apply<P, Q, CS, MR, MC, KJ, (O == 0)>(a, y, vc);
     }
 }
 
-template <int P, int Q, int MR, int MC, int KJ, int O>
+template <int P, int Q, bool CS, int MR, int MC, int KJ, int O>
 __device__ __forceinline__ void hess_all(double2 (&a)[MR][MC], double2 (&y)[MC], int m, int pr, int pc,
                                          double2* __restrict__ vb) {
     if constexpr (KJ < MC) {
         if constexpr (Q * KJ + Q <= O) {  // the phase lies wholly in the padding
-            hess_all<P, Q, MR, MC, KJ + 1, O>(a, y, m, pr, pc, vb);
+            hess_all<P, Q, CS, MR, MC, KJ + 1, O>(a, y, m, pr, pc, vb);
             return;
         }
         if (Q * KJ > O + m - 3) return;
-        hess_phase<P, Q, MR, MC, KJ, O>(a, y, m, pr, pc, vb);
-        hess_all<P, Q, MR, MC, KJ + 1, O>(a, y, m, pr, pc, vb);
+        hess_phase<P, Q, CS, MR, MC, KJ, O>(a, y, m, pr, pc, vb);
+        hess_all<P, Q, CS, MR, MC, KJ + 1, O>(a, y, m, pr, pc, vb);
     }
 }
 
@@ -651,9 +749,11 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     constexpr int W = 64 / G;
     int lane = threadIdx.x;
     if constexpr (LOOPED) asm volatile("" : "+v"(lane));
-    const int g = lane / G;
-    const int pr = lane % P;
-    const int pc = (lane / P) % Q;
+    constexpr bool CS = lane_map_cs<P, Q, MR, MC, TEAM, O>();
+    const int g = LaneMap<P, Q, CS>::g(lane);
+    const int pr = LaneMap<P, Q, CS>::pr(lane);
+    const int pc = LaneMap<P, Q, CS>::pc(lane);
+    const int gl = pc * P + pr;  // lane index within the group
     const int n = Np >> 1;
     const int m = 2 * s;
     constexpr int NT = 64 / T;
@@ -689,7 +789,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
     }
     for (int e = lane; e < W * 64; e += 64) L.vbuf[e] = cz();
     {
-        const int b = lane % G;  // each group lane b < n scans vertex b
+        const int b = gl;  // each group lane b < n scans vertex b
         if (b < n && ((mask >> b) & 1ull)) {
             const int pos = __popcll(mask & ((1ull << b) - 1ull));
             idx[pos] = b;
@@ -752,7 +852,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         double part = 0.0;
 #pragma unroll
         for (int i = 0; i < MR; ++i) part += cabs2(zr[i]);
-        const double norm2 = sum_cols<P>(part);
+        const double norm2 = sum_cols<P, CS>(part);
         const double2 x0 = dvec[idx[s]];  // z_0 = loop weight of the partner of vertex 0
         double scale;
         double2 vhead;
@@ -762,21 +862,13 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
         for (int i = 0; i < MR; ++i) vr[i] = (pr + P * i == o) ? vhead : cscale(zr[i], scale);
 #pragma unroll
         for (int k = 0; k < MC; ++k) vc[k] = (pc + Q * k == o) ? vhead : cscale(zc[k], scale);
-#pragma unroll
-        for (int k = 0; k < MC; ++k) {
-            double2 w = cz();
-#pragma unroll
-            for (int i = 0; i < MR; ++i) w = cfma_ca(vr[i], a[i][k], w);
-            w = csum_cols<P>(w);
-#pragma unroll
-            for (int i = 0; i < MR; ++i) a[i][k] = cfms(vr[i], w, a[i][k]);
-        }
-        right_apply<P, Q, MR, MC, 0, (O == 0)>(a, y, vc);
+        left_apply<P, CS, MR, MC, 0, 0>(a, vr);
+        right_apply<P, Q, CS, MR, MC, 0, (O == 0)>(a, y, vc);
     }
-    if (lane % G == 0) nb[1] = alpha;
+    if (gl == 0) nb[1] = alpha;
 
     // Householder reduction of the C block
-    hess_all<P, Q, MR, MC, 0, O>(a, y, m, pr, pc, vb);
+    hess_all<P, Q, CS, MR, MC, 0, O>(a, y, m, pr, pc, vb);
     // vbuf and idx are dead from here on; the La Budde ring reuses their space
     wave_sync();
 

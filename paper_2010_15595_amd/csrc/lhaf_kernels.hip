@@ -393,8 +393,11 @@ __global__ void __launch_bounds__(64) scalar_set_kernel(double2* __restrict__ ou
     }
 }
 
-// Self-check of the cross-lane sums used above: in[64] -> out[4 * 64]
-// (octet sums, stride-8 sums, readlane of lane 37, wave_shr:1).
+// Self-check of the cross-lane sums used above: in[64] -> out[1408]
+// (octet sums, stride-8 sums, readlane of lane 37, wave_shr:1, the two swaps,
+// six stride-8 sums at once (the 8x8 grid's row sums and the column-swap map's
+// column sums), four row sums of the default 8x4 map and four sums over lane
+// quads (the column-swap map's row sums)).
 __global__ void __launch_bounds__(64) selftest_kernel(const double* __restrict__ in, double* __restrict__ out) {
     const int l = threadIdx.x;
     const double x = in[l];
@@ -412,11 +415,14 @@ __global__ void __launch_bounds__(64) selftest_kernel(const double* __restrict__
     out[384 + l] = a;
     out[448 + l] = b;
     double v[6] = {x, 2.0 * x, 3.0 * x, -x, 0.5 * x, 7.0 * x};
-    rowsum_many<8, 8, 6>(v);
+    rowsum_many<8, 8, false, 6>(v);
     for (int j = 0; j < 6; ++j) out[512 + 64 * j + l] = v[j];
     double w[4] = {x, -2.0 * x, 3.0 * x, 0.25 * x};
-    rowsum_many<8, 4, 4>(w);
+    rowsum_many<8, 4, false, 4>(w);
     for (int j = 0; j < 4; ++j) out[896 + 64 * j + l] = w[j];
+    double u[4] = {x, 0.5 * x, -3.0 * x, 2.0 * x};
+    rowsum_many<8, 4, true, 4>(u);
+    for (int j = 0; j < 4; ++j) out[1152 + 64 * j + l] = u[j];
 }
 
 // ---------------------------------------------------------------- launchers
