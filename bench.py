@@ -32,18 +32,18 @@ TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_
                    "paper_2010_15595_amd/csrc/charpoly_l88.hip", "paper_2010_15595_amd/csrc/charpoly_l84.hip",
                    "paper_2010_15595_amd/csrc/charpoly_l44.hip")
 TRAFFIC = {
-    "sha256": "caee5e58fbb8de84ac5dcbf355be710e54b7d36a8185e7e7e70a59cbfc931b39",
+    "sha256": "7ac1e3023aeaa931845fab7c9393edf565b032a525f07f7b6a89853c34dcee15",
     "kernels": {  # FETCH_SIZE / WRITE_SIZE KiB per dispatch
-        "charpoly_kernel<8, 4, 3, 6, double2, 32, 0>": (1281331, 898611840),  # 625.6 / 877550.6
-        "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1393664, 898611840),  # 680.5 / 877550.6
-        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (1202944, 770238720),  # 587.4 / 752186.2
-        "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>": (1136998, 770238720),  # 555.2 / 752186.2
-        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (1138080, 706052160),  # 555.7 / 689504.1
-        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1291200, 706052160),  # 630.5 / 689504.1
-        "charpoly_kernel<4, 4, 5, 5, double2, 64, 2>": (1397440, 882565200),  # 682.3 / 861880.1
-        "charpoly_kernel<8, 4, 4, 8, double2, 64, 0>": (1314496, 882565200),  # 641.8 / 861880.1
-        "charpoly_kernel<4, 4, 4, 4, double2, 64, 0>": (1131968, 467240400),  # 552.7 / 456289.5
-        "charpoly_kernel<8, 8, 5, 5, double2, 64, 6>": (1038464, 467240400),  # 507.1 / 456289.5
+        "charpoly_kernel<8, 4, 3, 6, double2, 64, 0>": (1285274, 898611840),  # 627.6 / 877550.6
+        "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1398989, 898611840),  # 683.1 / 877550.6
+        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (1206195, 770238720),  # 589.0 / 752186.2
+        "charpoly_kernel<8, 4, 4, 7, double2, 64, 0>": (1287142, 770238720),  # 628.5 / 752186.2
+        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (1142240, 706052160),  # 557.7 / 689504.1
+        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1290144, 706052160),  # 630.0 / 689504.1
+        "charpoly_kernel<4, 4, 5, 5, double2, 64, 2>": (1403392, 882565200),  # 685.2 / 861880.1
+        "charpoly_kernel<8, 4, 4, 8, double2, 64, 0>": (1301248, 882565200),  # 635.4 / 861880.1
+        "charpoly_kernel<4, 4, 4, 4, double2, 64, 0>": (1136512, 467240400),  # 554.9 / 456289.5
+        "charpoly_kernel<8, 8, 5, 5, double2, 64, 6>": (1039168, 467240400),  # 507.4 / 456289.5
     },
 }
 

@@ -33,8 +33,9 @@
 // owns rows r = pr + P i (i < MR) and columns c = pc + Q k (k < MC).  Column
 // sums reduce over the P consecutive lanes (DPP quad_perm / row_half_mirror),
 // row sums over the Q lanes of stride P (DPP row_ror plus the gfx950
-// permlane16/32 swaps).  Lane grids: 8x8 (one subset per wave), 8x4 (two),
-// 4x4 (four); the choice per subset size is made by the host (autotuned).
+// permlane16/32 swaps); a few 8x4 instances use the column-swap map instead
+// (LaneMap below).  Lane grids: 8x8 (one subset per wave), 8x4 (two), 4x4
+// (four); the choice per subset size is made by the host (autotuned).
 
 #include "lhaf_kernels.h"
 
@@ -185,9 +186,9 @@ __device__ __forceinline__ uint64_t colex_next(uint64_t mask) {
 //    two columns for about the price of one), row sums over lane bits 0..1 (DPP
 //    quad permutations).  It issues fewer instructions and holds fewer
 //    registers; it is used where that lifts an instance to a second wave per
-//    SIMD (the one-team 8 x 4 tiles of 7 and 8 local columns with C at offset
-//    0), since elsewhere its longer chains of dependent swaps cost more than
-//    the instructions it saves.
+//    SIMD (the 8 x 4 tiles of 7 and 8 local columns with C at offset 0, with
+//    either La Budde team width), since elsewhere its longer chains of
+//    dependent swaps cost more than the instructions it saves.
 template <int P, int Q, bool CS>
 struct LaneMap {
     __device__ static int pr(int l) { return l % P; }
@@ -202,7 +203,7 @@ struct LaneMap<8, 4, true> {
 };
 template <int P, int Q, int MR, int MC, int TEAM, int O>
 constexpr bool lane_map_cs() {
-    return P == 8 && Q == 4 && TEAM == 64 && MR == 4 && MC >= 7 && O == 0;
+    return P == 8 && Q == 4 && MR == 4 && MC >= 7 && O == 0;
 }
 
 // Sums of NV values over the 8 lanes {l mod 8 + 8 q : q = 0..7}, all at once.
