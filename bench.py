@@ -32,18 +32,18 @@ TRAFFIC_SOURCES = ("paper_2010_15595_amd/csrc/lhaf_device.h", "paper_2010_15595_
                    "paper_2010_15595_amd/csrc/charpoly_l88.hip", "paper_2010_15595_amd/csrc/charpoly_l84.hip",
                    "paper_2010_15595_amd/csrc/charpoly_l44.hip")
 TRAFFIC = {
-    "sha256": "7ac1e3023aeaa931845fab7c9393edf565b032a525f07f7b6a89853c34dcee15",
+    "sha256": "6b2e424ae8298050ff7b6175df2aea57b3ec8a99a729673c550b9eb9d629ac1e",
     "kernels": {  # FETCH_SIZE / WRITE_SIZE KiB per dispatch
-        "charpoly_kernel<8, 4, 3, 6, double2, 64, 0>": (1285274, 898611840),  # 627.6 / 877550.6
-        "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1398989, 898611840),  # 683.1 / 877550.6
-        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (1206195, 770238720),  # 589.0 / 752186.2
-        "charpoly_kernel<8, 4, 4, 7, double2, 64, 0>": (1287142, 770238720),  # 628.5 / 752186.2
-        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (1142240, 706052160),  # 557.7 / 689504.1
-        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1290144, 706052160),  # 630.0 / 689504.1
-        "charpoly_kernel<4, 4, 5, 5, double2, 64, 2>": (1403392, 882565200),  # 685.2 / 861880.1
-        "charpoly_kernel<8, 4, 4, 8, double2, 64, 0>": (1301248, 882565200),  # 635.4 / 861880.1
-        "charpoly_kernel<4, 4, 4, 4, double2, 64, 0>": (1136512, 467240400),  # 554.9 / 456289.5
-        "charpoly_kernel<8, 8, 5, 5, double2, 64, 6>": (1039168, 467240400),  # 507.4 / 456289.5
+        "charpoly_kernel<8, 4, 3, 6, double2, 64, 0>": (1960755, 899399066),  # 957.4 / 878319.4
+        "charpoly_kernel<8, 4, 4, 7, double2, 64, 2>": (1380634, 898611840),  # 674.1 / 877550.6
+        "charpoly_kernel<8, 4, 3, 6, double2, 64, 2>": (1198259, 770238720),  # 585.1 / 752186.2
+        "charpoly_kernel<8, 8, 4, 4, double2, 64, 4>": (1136717, 770238720),  # 555.0 / 752186.2
+        "charpoly_kernel<8, 4, 3, 5, double2, 64, 0>": (1140992, 706052160),  # 557.1 / 689504.1
+        "charpoly_kernel<8, 4, 4, 8, double2, 64, 2>": (1281472, 706052160),  # 625.7 / 689504.1
+        "charpoly_kernel<4, 4, 5, 5, double2, 64, 2>": (1404928, 882565200),  # 686.0 / 861880.1
+        "charpoly_kernel<8, 4, 4, 8, double2, 64, 0>": (1309888, 882565200),  # 639.6 / 861880.1
+        "charpoly_kernel<4, 4, 4, 4, double2, 64, 0>": (1136128, 467240400),  # 554.8 / 456289.5
+        "charpoly_kernel<8, 8, 5, 5, double2, 64, 6>": (1040064, 467240400),  # 507.8 / 456289.5
     },
 }
 

@@ -185,10 +185,11 @@ __device__ __forceinline__ uint64_t colex_next(uint64_t mask) {
 //    over lane bits 3..5 (row_ror:8 and the two permlane swaps, which reduce
 //    two columns for about the price of one), row sums over lane bits 0..1 (DPP
 //    quad permutations).  It issues fewer instructions and holds fewer
-//    registers; it is used where that lifts an instance to a second wave per
-//    SIMD (the 8 x 4 tiles of 7 and 8 local columns with C at offset 0, with
-//    either La Budde team width), since elsewhere its longer chains of
-//    dependent swaps cost more than the instructions it saves.
+//    registers; it is used where that gains an instance a wave per SIMD (the
+//    8 x 4 tiles of 7 and 8 local columns with C at offset 0, with either La
+//    Budde team width, and the one-team 3 x 6 tile at offset 0 together with
+//    charpoly_min_waves), since elsewhere its longer chains of dependent swaps
+//    cost more than the instructions it saves.
 template <int P, int Q, bool CS>
 struct LaneMap {
     __device__ static int pr(int l) { return l % P; }
@@ -203,7 +204,15 @@ struct LaneMap<8, 4, true> {
 };
 template <int P, int Q, int MR, int MC, int TEAM, int O>
 constexpr bool lane_map_cs() {
-    return P == 8 && Q == 4 && MR == 4 && MC >= 7 && O == 0;
+    return P == 8 && Q == 4 && O == 0 && ((MR == 4 && MC >= 7) || (MR == 3 && MC == 6 && TEAM == 64));
+}
+// Waves per SIMD the compiler is held to: the FP64 one-team 8 x 4 instance with
+// the 3 x 6 tile at offset 0 takes 172 registers with the column-swap map, 4
+// above the three-wave limit; held to three waves it spills two of them (8
+// bytes of scratch per lane) and runs 12% faster than at two waves.
+template <int P, int Q, int MR, int MC, class V, int TEAM, int O>
+constexpr int charpoly_min_waves() {
+    return (P == 8 && Q == 4 && MR == 3 && MC == 6 && TEAM == 64 && O == 0 && sizeof(V) == sizeof(double2)) ? 3 : 1;
 }
 
 // Sums of NV values over the 8 lanes {l mod 8 + 8 q : q = 0..7}, all at once.
@@ -921,7 +930,7 @@ __device__ __forceinline__ void charpoly_wave(const double2* __restrict__ A0, co
 
 
 template <int P, int Q, int MR, int MC, class V, int TEAM, int O>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, (charpoly_min_waves<P, Q, MR, MC, V, TEAM, O>()))
     charpoly_kernel(const double2* __restrict__ A0, const double2* __restrict__ dvec, int Np, int s, uint64_t rank0,
                     uint64_t count, const uint64_t* __restrict__ masks, const uint64_t* __restrict__ binom, int D,
                     const int4* __restrict__ lbm, V* __restrict__ Eout) {
