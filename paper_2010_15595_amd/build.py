@@ -22,14 +22,22 @@ SOURCES = ["charpoly_l88.hip", "charpoly_l84.hip", "charpoly_l44.hip", "lhaf_ker
            "sampler_kernels.hip", "gbs_sampler.cpp", "lhaf_lds.hip", "gbs_noalloc.cpp"]
 
 
+# The compiler's per-kernel resource report (registers, scratch, waves per
+# SIMD) of every kernel source, kept beside the objects for the tests.
+RESOURCES = "-Rpass-analysis=kernel-resource-usage"
+
+
 def _compile(src):
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *COMMON, RESOURCES, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    if src.endswith(".hip"):
+        with open(os.path.join(BUILD, src + ".resources.txt"), "w") as f:
+            f.write(r.stderr)
     return obj
 
 
