@@ -721,8 +721,10 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the subset sum would shard by "
-              "pair-subset rank ranges across GPUs, which this build does not launch.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the subset sum shards by "
+              "pair-subset rank ranges (gbs_lhaf_device_shard computes one GPU's share, "
+              "--workload shard times G shares on one GPU), but no multi-GPU launch is provided.",
+              file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
 
